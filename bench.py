@@ -1,0 +1,224 @@
+"""Throughput of the N-body hot path on one MI355X.
+
+One step = one forward + adjoint pass over a rollout of R KDK steps of the
+scale-2^20 workload (N = 1,048,576 equal-mass Plummer sphere, eps = 2^-10,
+dt = 2^-11, FP32 pair arithmetic with tile-compensated FP64 sums, FP64
+positions and drift; R = 10 by default):
+  * FP64 energy / momentum diagnostics of the initial state;
+  * the forward rollout: a(x_0), then R KDK steps (R+1 force evaluations),
+    with the state checkpointed every 20 steps;
+  * FP64 diagnostics of the final state;
+  * the adjoint walk back over the R steps from the final state (R+1 fused
+    adjoint pair passes, each also giving a(x) for the walk-back).
+Inputs are resident in HBM before timing starts. `value` counts pair
+interactions of the force and adjoint kernels, N^2 per pass, per second of
+the whole step. Per-kernel device times come from the library's own HIP
+events around each launch over the timed steps (nbody_profile_*).
+
+Printed: one JSON line (the last line of stdout).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import ctypes
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK = 157.3e12      # MI355X published FP32 vector peak (counts packed FP32)
+FP32_NONPACKED_PEAK = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+FLOP_PER_FORCE_PAIR = 20         # 3 sub + 3 FMA + 3 mul + 3 FMA (FMA = 2) + 2 for rsqrt
+FLOP_PER_ADJOINT_PAIR = 55       # count of the fused adjoint pair body, same convention
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="scale-2^20")
+    ap.add_argument("--rollout", type=int, default=10, help="KDK steps per forward+adjoint pass")
+    ap.add_argument("--prec", default="mix_tilec")
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="sinks in the CPU-oracle baseline sample (0: skip)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2411_18889_amd as nb
+    from nbody_inputs import WORKLOADS, make_state, random_unit_vectors
+    from paper_2411_18889_amd import _lib
+
+    w = WORKLOADS[args.workload]
+    prec, R, K = args.prec, args.rollout, 20
+    dev = torch.device("cuda:0")
+    print("device:", nb.device_info(), flush=True)
+    t0 = time.time()
+    x0, v0, m0 = make_state(w)
+    n = x0.shape[1]
+    pdt, mdt = nb.pos_dtype(prec), nb.mass_dtype(prec)
+    X0 = torch.tensor(x0, dtype=pdt, device=dev)
+    V0 = torch.tensor(v0, dtype=pdt, device=dev)
+    M = torch.tensor(m0, dtype=mdt, device=dev)
+    lam0 = torch.tensor(random_unit_vectors((3, n), 99), dtype=pdt, device=dev)
+    x, v, acc = torch.empty_like(X0), torch.empty_like(X0), torch.empty_like(X0)
+    lx, lv = torch.empty_like(X0), torch.empty_like(X0)
+    lm = torch.empty(n, dtype=torch.float64, device=dev)
+    ckpt = torch.empty((R // K + 1, 9 * n), dtype=pdt, device=dev)
+    d0, d1 = (torch.empty(13, dtype=torch.float64, device=dev) for _ in range(2))
+    print("inputs ready: N=%d (%.1f s)" % (n, time.time() - t0), flush=True)
+
+    L = _lib.lib()
+    prof = _lib.nb_profile_t()
+
+    stream = torch.cuda.current_stream()
+    pass_events = []
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def one_step():
+        x.copy_(X0)
+        v.copy_(V0)
+        nb.diag(x, v, M, w.eps, prec=prec, out=d0)
+        e0 = ev()
+        nb.step(x, v, M, acc, w.eps, w.dt, R, prec=prec, ckpt=ckpt, ckpt_every=K)
+        e1 = ev()
+        nb.diag(x, v, M, w.eps, prec=prec, out=d1)
+        lx.copy_(lam0)
+        lv.zero_()
+        lm.zero_()
+        e2 = ev()
+        nb.step_adjoint(x, v, M, acc, lx, lv, lm, w.eps, w.dt, R, prec=prec, entry_half=True,
+                        ckpt=ckpt, ckpt_every=K, step_end=R)
+        e3 = ev()
+        pass_events.append((e0, e1, e2, e3))
+
+    for i in range(args.warmup):
+        one_step()
+        torch.cuda.synchronize()
+        print("warmup step %d done" % i, flush=True)
+
+    pass_events.clear()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    _lib.check(L.nbody_profile_begin(), "nbody_profile_begin")
+    ev0.record(stream)
+    wall0 = time.time()
+    for i in range(args.steps):
+        one_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    _lib.check(L.nbody_profile_end(ctypes.byref(prof)), "nbody_profile_end")
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    print("timed %d steps: %.1f ms/step (wall %.1f s)" % (args.steps, ms_step, wall), flush=True)
+
+    passes_fwd, passes_adj = R + 1, R + 1
+    interactions = float(n) * n * (passes_fwd + passes_adj)
+    value = interactions / (ms_step * 1e-3) / 1e9
+
+    f_ms = prof.ms[0] / max(1, prof.calls[0])
+    a_ms = prof.ms[1] / max(1, prof.calls[1])
+    force_tflops = FLOP_PER_FORCE_PAIR * float(n) * n / (f_ms * 1e-3) / 1e12
+    adj_tflops = FLOP_PER_ADJOINT_PAIR * float(n) * n / (a_ms * 1e-3) / 1e12
+    kinds = ["force", "adjoint", "update", "diag", "copy"]
+    per_kind = {k: {"ms_per_step": prof.ms[i] / args.steps, "calls": int(prof.calls[i])}
+                for i, k in enumerate(kinds)}
+    fwd_ms = sum(a.elapsed_time(b) for a, b, _, _ in pass_events) / len(pass_events)
+    adj_ms = sum(c.elapsed_time(d) for _, _, c, d in pass_events) / len(pass_events)
+    dom = "adjoint" if prof.ms[1] >= prof.ms[0] else "force"
+    if dom == "adjoint":
+        roof = {"kernel": "adjoint_kernel (fused force + J^T lam + G^T lam)", "bound": "alu",
+                "achieved": adj_tflops, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": adj_tflops * 1e12 / FP32_VECTOR_PEAK, "traffic": None,
+                "flop_per_pair": FLOP_PER_ADJOINT_PAIR, "avg_launch_ms": a_ms}
+    else:
+        roof = {"kernel": "force_kernel", "bound": "alu", "achieved": force_tflops,
+                "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK, "traffic": None,
+                "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
+    force_roof = {"kernel": "force_kernel", "bound": "alu", "achieved": force_tflops,
+                  "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                  "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK,
+                  "frac_nonpacked_peak": force_tflops * 1e12 / FP32_NONPACKED_PEAK,
+                  "ginteractions_per_s": float(n) * n / (f_ms * 1e-3) / 1e9,
+                  "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
+
+    D0 = nb.diag_dict(d0)
+    D1 = nb.diag_dict(d1)
+    dE = (D1["E"] - D0["E"]) / abs(D0["E"])
+
+    cpu = None
+    rel_err = None
+    if args.cpu_sample > 0:
+        import oracle
+        # forward force of the initial state on the GPU, then the same sinks
+        # one by one on the host cores
+        xs = torch.tensor(x0, dtype=pdt, device=dev)
+        a_gpu = nb.accel(xs, M, w.eps, prec=prec).cpu().numpy()
+        xh, mh = xs.cpu().numpy().astype(np.float64), M.cpu().numpy().astype(np.float64)
+        rng = np.random.default_rng(1234)
+        idx = np.sort(rng.choice(n, size=min(args.cpu_sample, n), replace=False))
+        tc = time.time()
+        ref = oracle.accel_sampled(xh, mh, w.eps, idx)
+        tcpu = time.time() - tc
+        rel_err = float(np.linalg.norm(a_gpu[:, idx] - ref) / np.linalg.norm(ref))
+        cpu = {"value": len(idx) * float(n) / tcpu / 1e9, "unit": "Ginteractions/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "%d seeded sinks x all %d sources, FP64 force (%.1f s)"
+                         % (len(idx), n, tcpu)}
+        print("cpu oracle: %.3f Ginteractions/s on %d threads; GPU force rel err %.3g"
+              % (cpu["value"], cpu["cores"], rel_err), flush=True)
+
+    out = {
+        "metric": "Ginteractions/s & % FP32 vector peak; adjoint/forward time at rel err ≤1e-5",
+        "value": value,
+        "unit": "Ginteractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair arithmetic, f64 sums/state" if prec.startswith("mix") else prec,
+        "data": "synthetic: seeded Plummer sphere",
+        "config": {"workload": w.name, "n": n, "eps": w.eps, "dt": w.dt, "rollout_steps": R,
+                   "ckpt_every": K, "precision": prec,
+                   "step": "diag + forward rollout (R+1 force passes) + diag + adjoint walk "
+                           "(R+1 fused passes)"},
+        "roofline": roof,
+        "force_kernel": force_roof,
+        "forward_pass_ms": fwd_ms,
+        "adjoint_pass_ms": adj_ms,
+        "adjoint_over_forward": adj_ms / fwd_ms,
+        "adjoint_over_forward_kernel": a_ms / f_ms,
+        "force_rel_err_sampled": rel_err,
+        "energy_drift": dE,
+        "per_kind": per_kind,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

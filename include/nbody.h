@@ -1,0 +1,251 @@
+/*
+ * nbody.h -- C ABI of libnbody.so, a direct-summation gravitational N-body
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * What it computes
+ *   The softened pairwise acceleration of Eq. (1) of the paper (section
+ *   "N-body simulation"),
+ *       a_i = G * sum_j m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2),
+ *   evaluated for a set of sinks i against a set of sources j (the paper's
+ *   calc_acc takes Ni sinks and Nj sources), inside a second-order
+ *   kick-drift-kick (KDK) leapfrog, with a reverse-mode adjoint of that
+ *   leapfrog and FP64 energy / momentum diagnostics. The paper's listing
+ *   includes the j = i term, which contributes exactly zero to a_i when
+ *   eps > 0; so does this library.
+ *
+ * Data layout (all entry points)
+ *   Structure of arrays. A position, velocity, acceleration or adjoint array
+ *   of n particles is 3n contiguous elements: x[0..n), y[0..n), z[0..n).
+ *   Masses and potentials are n elements. The element types are set by the
+ *   precision policy `prec` (nb_prec below). Every pointer must be aligned to
+ *   its element size. All device pointers are HIP device (or managed)
+ *   memory owned by the caller; the library never allocates, frees or
+ *   retains memory. Scratch memory comes from the caller's workspace `ws`
+ *   (device memory, 256-byte aligned, at least nbody_workspace_size() bytes;
+ *   may be NULL when that size is 0).
+ *
+ * Streams and synchronisation
+ *   `stream` is a hipStream_t (NULL = the default stream). Every entry point
+ *   only enqueues work on it and returns; nothing waits for the device. Two
+ *   calls on different streams may run concurrently if they do not share
+ *   writable buffers or workspace. Arguments are validated before any HIP
+ *   call; a rejected call enqueues nothing.
+ *
+ * Errors
+ *   Every entry point returns an nb_status. No C++ exception crosses the
+ *   ABI. NB_EDEVICE means a HIP call failed; the HIP error is available via
+ *   nbody_last_hip_error().
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nb_status {
+    NB_OK = 0,
+    NB_EINVAL = 1,       /* invalid argument (see each entry point)           */
+    NB_EWORKSPACE = 2,   /* workspace NULL, misaligned or smaller than needed */
+    NB_EUNSUPPORTED = 3, /* precision / operation / launch shape not provided */
+    NB_ENODEV = 4,       /* no gfx950 device is current                        */
+    NB_EDEVICE = 5       /* a HIP call failed (launch or copy)                 */
+} nb_status;
+
+/*
+ * Precision policies. "pos" is the element type of positions, velocities,
+ * accelerations, potentials and position/velocity adjoints; "mass" that of
+ * masses; the mass adjoint is always double.
+ *
+ *   NB_F64        pos double, mass double. Pair arithmetic and sums in FP64
+ *                 (hardware reciprocal square root refined by two Newton
+ *                 steps).
+ *   NB_F32        pos float,  mass float.  Pair arithmetic in FP32 with the
+ *                 hardware reciprocal square root; per-particle sums are FP32
+ *                 running sums, as the paper's listing.
+ *   NB_MIX_ACC32  pos double, mass float. Positions are rounded to FP32 for
+ *                 the pair arithmetic (FP32, as NB_F32); FP32 running sums.
+ *                 Kick, drift and everything O(N) stay in FP64.
+ *   NB_MIX_KAHAN  as NB_MIX_ACC32, but each running sum is Kahan-compensated
+ *                 in FP32.
+ *   NB_MIX_ACC64  as NB_MIX_ACC32, but each FP32 pair term is summed in FP64.
+ *   NB_MIX_TILEC  as NB_MIX_ACC32, but the FP32 running sum restarts at every
+ *                 j-tile and the tile sums are added in FP64.
+ */
+typedef enum nb_prec {
+    NB_F64 = 0,
+    NB_F32 = 1,
+    NB_MIX_ACC32 = 2,
+    NB_MIX_KAHAN = 3,
+    NB_MIX_ACC64 = 4,
+    NB_MIX_TILEC = 5
+} nb_prec;
+
+/* Operation codes for nbody_workspace_size(). */
+typedef enum nb_op {
+    NB_OP_ACCEL = 0,
+    NB_OP_STEP = 1,
+    NB_OP_ADJOINT = 2,
+    NB_OP_DIAG = 3
+} nb_op;
+
+/* nbody_step() flags */
+#define NB_ACC_VALID 0x1u      /* acc already holds a(x) on entry            */
+
+/* nbody_step_adjoint() flags */
+#define NB_ADJ_ENTRY_HALF 0x1u /* apply the h-weighted position adjoint at the
+                                  entry state (set on the call that starts a
+                                  backward pass at the rollout's last step)   */
+#define NB_ADJ_EXIT_FULL 0x2u  /* weight the position adjoint at the exit
+                                  state by dt instead of h (set on every call
+                                  that does not end at the rollout's step 0)  */
+
+/* Explicit launch shape for nbody_accel_ex(); 0 in a field = library choice. */
+typedef struct nb_launch {
+    int32_t i_per_lane; /* sinks per lane: 1, 2 or 4                          */
+    int32_t block;      /* threads per workgroup (= j-tile length): 64..1024,
+                           a multiple of 64                                    */
+    int32_t split;      /* j-split: number of source ranges per sink, 1..256;
+                           partial sums are combined in a fixed order         */
+} nb_launch;
+
+/*
+ * nbody_accel -- accelerations of ni sinks from nj sources, Eq. (1).
+ *
+ *   xi   [3*ni] pos   sink positions (device)
+ *   xj   [3*nj] pos   source positions (device); xi == xj with ni == nj means
+ *                     one set acting on itself
+ *   mj   [nj]   mass  source masses (device)
+ *   eps  softening length: finite and > 0 (>= 2^-40 in the FP32 policies)
+ *   G    gravitational constant, finite
+ *   acc  [3*ni] pos   output accelerations (device); must not overlap inputs
+ *   pot  [ni]   pos   optional output (NULL to skip): the potential
+ *                     phi_i = -G sum_j m_j / sqrt(|r_j - r_i|^2 + eps^2),
+ *                     with the j = i term removed when xi == xj (the paper's
+ *                     CALCULATE_POTENTIAL branch sums it in; here it is
+ *                     subtracted once per sink after the sum)
+ *   ws, ws_bytes      workspace, nbody_workspace_size(NB_OP_ACCEL, max(ni,nj), prec)
+ *   stream            hipStream_t
+ * Returns NB_EINVAL for ni < 1, nj < 1, ni or nj > 2^30, bad eps or G, a
+ * NULL or misaligned pointer, or xi == xj with ni != nj.
+ */
+int nbody_accel(int64_t ni, const void *xi, int64_t nj, const void *xj,
+                const void *mj, double eps, double G, int prec, void *acc,
+                void *pot, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * nbody_accel_ex -- nbody_accel with an explicit launch shape (for tuning and
+ * for tests that a result does not depend on the shape). NULL launch = the
+ * library's choice. NB_EUNSUPPORTED for a shape outside nb_launch's limits.
+ */
+int nbody_accel_ex(int64_t ni, const void *xi, int64_t nj, const void *xj,
+                   const void *mj, double eps, double G, int prec, void *acc,
+                   void *pot, const nb_launch *launch, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/*
+ * nbody_step -- nsteps KDK leapfrog steps of size dt (h = dt/2), in place:
+ *   v <- v + h a(x);  x <- x + dt v;  a <- a(x);  v <- v + h a,
+ * the pair forces of Eq. (1) with the j = i term (zero) included.
+ *
+ *   n          particle count, 1..2^30
+ *   x, v [3n]  pos, in/out (device)
+ *   m    [n]   mass (device)
+ *   acc  [3n]  pos, in/out: on entry a(x) if flags has NB_ACC_VALID (else it
+ *              is computed first); on exit a(x) of the final state
+ *   eps, G     as nbody_accel;  dt finite;  nsteps >= 0
+ *   ckpt       optional (NULL to skip) device buffer of
+ *              (nsteps / ckpt_every + 1) slots of 9n pos elements; slot k
+ *              receives x, v, acc (3n each, in that order) at step
+ *              k * ckpt_every, slot 0 being the entry state
+ *   ckpt_every checkpoint interval >= 1 (ignored when ckpt is NULL)
+ *   ws         workspace of nbody_workspace_size(NB_OP_STEP, n, prec) bytes
+ */
+int nbody_step(int64_t n, void *x, void *v, const void *m, void *acc,
+               double eps, double G, double dt, int64_t nsteps, int prec,
+               unsigned flags, void *ckpt, int64_t ckpt_every, void *ws,
+               size_t ws_bytes, void *stream);
+
+/*
+ * nbody_step_adjoint -- reverse-mode derivative of nbody_step, walking
+ * nsteps steps back from the entry state.
+ *
+ * On entry (x, v, acc) is the forward state at step k = step_end and
+ * (lam_x, lam_v) = dL/dx_k, dL/dv_k. On exit (x, v, acc) is the state at
+ * step k - nsteps and (lam_x, lam_v) = dL/dx, dL/dv there; lam_m has the
+ * mass derivative of those steps added. Per step n+1 -> n:
+ *   lam_v += dt lam_x;
+ *   the state is walked back by the time-reversed KDK step, or, when ckpt is
+ *   given and n is a multiple of ckpt_every, reloaded from slot n/ckpt_every;
+ *   lam_x += c J(x_n)^T lam_v and lam_m += c G(x_n)^T lam_v, where J and G
+ *   are the Jacobians of a(x, m) with respect to positions and masses,
+ *   c = dt inside the walk, and c = h or dt at the exit state
+ *   (NB_ADJ_EXIT_FULL). With NB_ADJ_ENTRY_HALF the same update with c = h is
+ *   first applied at the entry state.
+ *
+ *   lam_x, lam_v [3n] pos, in/out; lam_m [n] double, in/out (accumulates)
+ *   ckpt, ckpt_every  as written by nbody_step over the same rollout, or NULL
+ *   step_end   absolute step index of the entry state (used with ckpt only);
+ *              0 <= step_end - nsteps
+ *   other arguments as nbody_step; ws of nbody_workspace_size(NB_OP_ADJOINT)
+ */
+int nbody_step_adjoint(int64_t n, void *x, void *v, const void *m, void *acc,
+                       void *lam_x, void *lam_v, void *lam_m, double eps,
+                       double G, double dt, int64_t nsteps, int prec,
+                       unsigned flags, const void *ckpt, int64_t ckpt_every,
+                       int64_t step_end, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/*
+ * nbody_diag -- FP64 conserved quantities of a state (any policy; FP32
+ * inputs are promoted exactly). out (device, 13 doubles):
+ *   0 KE = 1/2 sum m|v|^2       1 PE = -G sum_{i<j} m_i m_j / sqrt(s_ij)
+ *   2 E = KE + PE               3..5 P = sum m v
+ *   6..8 L = sum m r x v        9..11 centre of mass     12 total mass
+ * ws of nbody_workspace_size(NB_OP_DIAG, n, prec) bytes.
+ */
+int nbody_diag(int64_t n, const void *x, const void *v, const void *m,
+               double eps, double G, int prec, double *out, void *ws,
+               size_t ws_bytes, void *stream);
+
+/*
+ * Device-time profile of the library's own launches (tooling; not part of the
+ * method). Between nbody_profile_begin() and nbody_profile_end() the calling
+ * thread's entry points record a HIP event before and after each group of
+ * launches of one kind, on the stream they launch on. nbody_profile_end()
+ * waits for those events, fills *out (may be NULL) and stops recording.
+ * Kinds: the pair-force kernel (with its split reduction), the fused adjoint
+ * kernel (with its split reduction), O(N) leapfrog updates, diagnostics,
+ * checkpoint copies. Not for use under stream capture.
+ */
+enum { NB_PROF_FORCE = 0, NB_PROF_ADJOINT = 1, NB_PROF_UPDATE = 2, NB_PROF_DIAG = 3,
+       NB_PROF_COPY = 4, NB_PROF_KINDS = 5 };
+typedef struct nb_profile {
+    double ms[NB_PROF_KINDS];       /* summed device milliseconds per kind    */
+    int64_t calls[NB_PROF_KINDS];   /* timed launch groups per kind           */
+} nb_profile;
+int nbody_profile_begin(void);
+int nbody_profile_end(nb_profile *out);
+
+/* Workspace bytes an operation needs for n particles (0 = none). For
+ * NB_OP_ACCEL pass max(ni, nj). Returns 0 for an invalid op or prec. */
+size_t nbody_workspace_size(int op, int64_t n, int prec);
+
+/* Static text for a status code. */
+const char *nbody_strerror(int status);
+
+/* The last HIP error code this thread saw inside the library (0 if none). */
+int nbody_last_hip_error(void);
+
+/* Writes a one-line description of the current device into buf (always
+ * NUL-terminated when len > 0). NB_ENODEV when no gfx950 device is there. */
+int nbody_device_info(char *buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

@@ -1,0 +1,174 @@
+"""Tensor-level binding of libnbody: argument checks and marshalling only.
+
+Every computation runs in the library's HIP kernels; this module only checks
+tensor dtypes, devices and shapes, sizes the workspace, and passes pointers
+and the current HIP stream through the C ABI.
+
+Layout: positions, velocities, accelerations and adjoints are (3, n)
+contiguous tensors (rows x, y, z); masses and potentials are (n,).
+Precision names: "f64", "f32", "mix_acc32", "mix_kahan", "mix_acc64",
+"mix_tilec" (see include/nbody.h).
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import PREC, check, nb_launch
+
+
+def pos_dtype(prec: str):
+    return torch.float32 if prec == "f32" else torch.float64
+
+
+def mass_dtype(prec: str):
+    return torch.float64 if prec == "f64" else torch.float32
+
+
+def _prec(prec: str) -> int:
+    if prec not in PREC:
+        raise ValueError("unknown precision %r (one of %s)" % (prec, sorted(PREC)))
+    return PREC[prec]
+
+
+def _vec(t, name, n, dtype, rows=3):
+    shape = (rows, n) if rows else (n,)
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if tuple(t.shape) != shape or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor, got %s" % (name, shape, tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace_size(op: int, n: int, prec: str) -> int:
+    return int(_lib.lib().nbody_workspace_size(op, int(n), _prec(prec)))
+
+
+def _workspace(op, n, prec, device):
+    nbytes = workspace_size(op, n, prec)
+    if nbytes == 0:
+        return None, ctypes.c_void_p(0), 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return ws, ctypes.c_void_p(ws.data_ptr()), nbytes
+
+
+def accel(x, m, eps, G=1.0, prec="mix_tilec", xj=None, potential=False, launch=None,
+          out=None, stream=None):
+    """a (3, ni) of the sinks x (3, ni) from the sources xj (3, nj) with masses m
+    (nj,) -- Eq. (1). xj=None: the set x acts on itself. potential=True also
+    returns phi (ni,)."""
+    p = _prec(prec)
+    pdt, mdt = pos_dtype(prec), mass_dtype(prec)
+    ni = x.shape[1]
+    src = x if xj is None else xj
+    nj = src.shape[1]
+    px = _vec(x, "x", ni, pdt)
+    pj = px if xj is None else _vec(xj, "xj", nj, pdt)
+    pm = _vec(m, "m", nj, mdt, rows=0)
+    acc = torch.empty((3, ni), dtype=pdt, device=x.device) if out is None else out
+    pa = _vec(acc, "out", ni, pdt)
+    pot = torch.empty(ni, dtype=pdt, device=x.device) if potential else None
+    pp = _vec(pot, "pot", ni, pdt, rows=0) if potential else ctypes.c_void_p(0)
+    ws, pws, nws = _workspace(_lib.NB_OP_ACCEL, max(ni, nj), prec, x.device)
+    L = _lib.lib()
+    if launch is None:
+        st = L.nbody_accel(ni, px, nj, pj, pm, float(eps), float(G), p, pa, pp, pws, nws,
+                           _stream(stream))
+    else:
+        ln = nb_launch(*[int(launch.get(k, 0)) for k in ("i_per_lane", "block", "split")])
+        if ln.split > 1:  # FP64 partials: split x 4 quantities x ni sinks
+            need = ln.split * 4 * ni * 8
+            if need > nws:
+                ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+                pws, nws = ctypes.c_void_p(ws.data_ptr()), need
+        st = L.nbody_accel_ex(ni, px, nj, pj, pm, float(eps), float(G), p, pa, pp,
+                              ctypes.byref(ln), pws, nws, _stream(stream))
+    check(st, "nbody_accel")
+    return (acc, pot) if potential else acc
+
+
+def step(x, v, m, acc, eps, dt, nsteps, G=1.0, prec="mix_tilec", acc_valid=False,
+         ckpt=None, ckpt_every=0, stream=None):
+    """nsteps KDK steps in place on x, v, acc. ckpt: optional tensor of
+    (nsteps // ckpt_every + 1, 9 n) pos elements receiving (x, v, acc) every
+    ckpt_every steps."""
+    p = _prec(prec)
+    pdt, mdt = pos_dtype(prec), mass_dtype(prec)
+    n = x.shape[1]
+    args = [_vec(x, "x", n, pdt), _vec(v, "v", n, pdt), _vec(m, "m", n, mdt, rows=0),
+            _vec(acc, "acc", n, pdt)]
+    if ckpt is not None:
+        slots = nsteps // ckpt_every + 1
+        pc = _vec(ckpt, "ckpt", 9 * n, pdt, rows=slots)
+    else:
+        pc = ctypes.c_void_p(0)
+    ws, pws, nws = _workspace(_lib.NB_OP_STEP, n, prec, x.device)
+    st = _lib.lib().nbody_step(n, *args, float(eps), float(G), float(dt), int(nsteps), p,
+                               _lib.NB_ACC_VALID if acc_valid else 0, pc, int(ckpt_every),
+                               pws, nws, _stream(stream))
+    check(st, "nbody_step")
+
+
+def step_adjoint(x, v, m, acc, lam_x, lam_v, lam_m, eps, dt, nsteps, G=1.0,
+                 prec="mix_tilec", entry_half=False, exit_full=False, ckpt=None,
+                 ckpt_every=0, step_end=0, stream=None):
+    """Walk nsteps KDK steps back from (x, v, acc), updating the adjoints
+    lam_x, lam_v (3, n) and lam_m (n, float64) in place."""
+    p = _prec(prec)
+    pdt, mdt = pos_dtype(prec), mass_dtype(prec)
+    n = x.shape[1]
+    args = [_vec(x, "x", n, pdt), _vec(v, "v", n, pdt), _vec(m, "m", n, mdt, rows=0),
+            _vec(acc, "acc", n, pdt), _vec(lam_x, "lam_x", n, pdt), _vec(lam_v, "lam_v", n, pdt),
+            _vec(lam_m, "lam_m", n, torch.float64, rows=0)]
+    if ckpt is not None:
+        slots = ckpt.shape[0]
+        pc = _vec(ckpt, "ckpt", 9 * n, pdt, rows=slots)
+    else:
+        pc = ctypes.c_void_p(0)
+    flags = (_lib.NB_ADJ_ENTRY_HALF if entry_half else 0) | (_lib.NB_ADJ_EXIT_FULL if exit_full else 0)
+    ws, pws, nws = _workspace(_lib.NB_OP_ADJOINT, n, prec, x.device)
+    st = _lib.lib().nbody_step_adjoint(n, *args, float(eps), float(G), float(dt), int(nsteps),
+                                       p, flags, pc, int(ckpt_every), int(step_end), pws, nws,
+                                       _stream(stream))
+    check(st, "nbody_step_adjoint")
+
+
+DIAG_FIELDS = ("KE", "PE", "E", "Px", "Py", "Pz", "Lx", "Ly", "Lz",
+               "COMx", "COMy", "COMz", "M")
+
+
+def diag(x, v, m, eps, G=1.0, prec="mix_tilec", stream=None, out=None):
+    """FP64 conserved quantities as a (13,) float64 device tensor (fields in
+    DIAG_FIELDS order)."""
+    p = _prec(prec)
+    pdt, mdt = pos_dtype(prec), mass_dtype(prec)
+    n = x.shape[1]
+    res = torch.empty(13, dtype=torch.float64, device=x.device) if out is None else out
+    ws, pws, nws = _workspace(_lib.NB_OP_DIAG, n, prec, x.device)
+    st = _lib.lib().nbody_diag(n, _vec(x, "x", n, pdt), _vec(v, "v", n, pdt),
+                               _vec(m, "m", n, mdt, rows=0), float(eps), float(G), p,
+                               _vec(res, "out", 13, torch.float64, rows=0), pws, nws,
+                               _stream(stream))
+    check(st, "nbody_diag")
+    return res
+
+
+def diag_dict(res) -> dict:
+    return dict(zip(DIAG_FIELDS, res.tolist()))
+
+
+def device_info() -> str:
+    buf = ctypes.create_string_buffer(256)
+    st = _lib.lib().nbody_device_info(buf, 256)
+    check(st, "nbody_device_info")
+    return buf.value.decode()

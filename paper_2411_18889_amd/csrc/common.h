@@ -1,0 +1,195 @@
+// Private header of libnbody: precision traits, per-sink accumulators and
+// the reciprocal square roots shared by the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nbody.h"
+
+namespace nb {
+
+// Fused multiply-add in the operands' own type (__builtin_fma alone would
+// promote float operands to double).
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------------------
+// Reciprocal square roots.
+//
+// FP32: the hardware v_rsq_f32 (about 1 ulp). The paper notes that a fast
+// approximate reciprocal square root is what makes this kernel fast on every
+// GPU it measured (section "N-body simulation").
+// FP64: v_rsq_f64 as a first guess, then two Newton-Raphson steps on
+// f(y) = y^-2 - s, i.e. y <- y + y (1 - s y^2) / 2, each roughly squaring the
+// relative error; the residual 1 - s y^2 is formed with an FMA.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rsqrt_pair(float s) { return __builtin_amdgcn_rsqf(s); }
+
+__device__ __forceinline__ double rsqrt_pair(double s) {
+    double y = __builtin_amdgcn_rsq(s);
+    double e = __builtin_fma(-s * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-s * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    return y;
+}
+
+// ---------------------------------------------------------------------------
+// Per-sink running sums (one component each).
+// ---------------------------------------------------------------------------
+
+// Plain running sum in the pair-arithmetic type T: s = fma(d, w, s), the
+// listing's accumulation.
+template <typename T>
+struct SumPlain {
+    T s;
+    __device__ __forceinline__ void init() { s = T(0); }
+    __device__ __forceinline__ void add_fma(T d, T w) { s = fmat(d, w, s); }
+    __device__ __forceinline__ void add(T t) { s += t; }
+    __device__ __forceinline__ void tile_end() {}
+    __device__ __forceinline__ double total() const { return double(s); }
+};
+
+// Kahan-compensated FP32 running sum. The term d*w - c is formed with one
+// FMA, then t = s + y; c = (t - s) - y recovers the rounding error of the
+// addition (exact when |s| >= |y|) and feeds it back into the next term.
+struct SumKahan {
+    float s, c;
+    __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
+    __device__ __forceinline__ void add_y(float y) {
+        float t = s + y;
+        // keep the compensation: no reassociation (no fast-math in this build)
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ void add_fma(float d, float w) { add_y(__builtin_fmaf(d, w, -c)); }
+    __device__ __forceinline__ void add(float t) { add_y(t - c); }
+    __device__ __forceinline__ void tile_end() {}
+    __device__ __forceinline__ double total() const { return double(s) - double(c); }
+};
+
+// FP32 terms summed in FP64: the exact product of the FP32 factors is added
+// with an FP64 FMA.
+struct SumWide {
+    double s;
+    __device__ __forceinline__ void init() { s = 0.0; }
+    __device__ __forceinline__ void add_fma(float d, float w) {
+        s = __builtin_fma(double(d), double(w), s);
+    }
+    __device__ __forceinline__ void add(float t) { s += double(t); }
+    __device__ __forceinline__ void tile_end() {}
+    __device__ __forceinline__ double total() const { return s; }
+};
+
+// FP32 running sum over one j-tile, folded into an FP64 total at the end of
+// every tile: FP32 cost per pair, and the FP32 error grows only with the tile
+// length instead of with N.
+struct SumTile {
+    float p;
+    double s;
+    __device__ __forceinline__ void init() { p = 0.f; s = 0.0; }
+    __device__ __forceinline__ void add_fma(float d, float w) { p = __builtin_fmaf(d, w, p); }
+    __device__ __forceinline__ void add(float t) { p += t; }
+    __device__ __forceinline__ void tile_end() { s += double(p); p = 0.f; }
+    __device__ __forceinline__ double total() const { return s + double(p); }
+};
+
+// ---------------------------------------------------------------------------
+// Precision traits: storage types and the pair-arithmetic type.
+// ---------------------------------------------------------------------------
+template <typename Pos, typename Mass, typename Calc, typename Sum>
+struct Policy {
+    using pos_t = Pos;    // positions, velocities, accelerations, adjoints
+    using mass_t = Mass;  // masses
+    using calc_t = Calc;  // pair arithmetic
+    using sum_t = Sum;    // per-sink running sum
+};
+
+using PolF64 = Policy<double, double, double, SumPlain<double>>;
+using PolF32 = Policy<float, float, float, SumPlain<float>>;
+using PolMixAcc32 = Policy<double, float, float, SumPlain<float>>;
+using PolMixKahan = Policy<double, float, float, SumKahan>;
+using PolMixAcc64 = Policy<double, float, float, SumWide>;
+using PolMixTileC = Policy<double, float, float, SumTile>;
+
+// 4-vector LDS record of the pair-arithmetic type.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+inline size_t pos_size(int prec) { return prec == NB_F32 ? 4 : 8; }
+inline size_t mass_size(int prec) { return (prec == NB_F64) ? 8 : 4; }
+
+// Calls f(PolicyTag{}) with the policy of `prec`; returns false if unknown.
+template <typename F>
+inline bool dispatch_prec(int prec, F&& f) {
+    switch (prec) {
+    case NB_F64: f(PolF64{}); return true;
+    case NB_F32: f(PolF32{}); return true;
+    case NB_MIX_ACC32: f(PolMixAcc32{}); return true;
+    case NB_MIX_KAHAN: f(PolMixKahan{}); return true;
+    case NB_MIX_ACC64: f(PolMixAcc64{}); return true;
+    case NB_MIX_TILEC: f(PolMixTileC{}); return true;
+    default: return false;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch shapes and the functions each kernel file provides.
+// ---------------------------------------------------------------------------
+struct Shape {
+    int ipl;    // sinks per lane
+    int block;  // threads per workgroup = j-tile length
+    int split;  // j-ranges per sink
+};
+
+// Library choice of shape for ni sinks, nj sources.
+Shape choose_force_shape(int prec, int64_t ni, int64_t nj);
+Shape choose_adjoint_shape(int prec, int64_t n);
+bool shape_supported(const Shape& s);
+
+// Workspace bytes of the split partials of a force / adjoint launch.
+size_t force_partials_bytes(const Shape& s, int64_t ni);
+size_t adjoint_partials_bytes(const Shape& s, int64_t n);
+
+// Force: acc (and pot) of ni sinks. self_set: xi and xj are the same set.
+hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi,
+                        int64_t nj, const void* xj, const void* mj, double eps,
+                        double G, bool self_set, void* acc, void* pot, void* ws,
+                        hipStream_t stream);
+
+// Fused adjoint pair pass at x with adjoint lam_v: computes a(x), J^T lam_v,
+// G^T lam_v and applies the epilogue
+//   lam_x += c J^T lam_v;  lam_m += c G^T lam_v;
+//   if update_state: acc = a(x); v = v - h acc.
+hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x,
+                          const void* m, const void* lam_v, double eps, double G,
+                          double c, bool update_state, double h, void* acc, void* v,
+                          void* lam_x, double* lam_m, void* ws, hipStream_t stream);
+
+// O(N) leapfrog kernels over the 3n components of a pos array.
+hipError_t launch_kick(int prec, int64_t n, void* v, const void* acc, double h,
+                       hipStream_t stream);
+hipError_t launch_kick_drift(int prec, int64_t n, void* x, void* v, const void* acc,
+                             double h, double dt, hipStream_t stream);
+// Reverse drift: lam_v += dt lam_x; v <- v - h acc; x <- x - dt v.
+hipError_t launch_reverse_drift(int prec, int64_t n, void* x, void* v, const void* acc,
+                                const void* lam_x, void* lam_v, double h, double dt,
+                                hipStream_t stream);
+// lam_v += dt lam_x only (before a checkpoint reload).
+hipError_t launch_axpy_pos(int prec, int64_t n3, void* y, const void* xv, double a,
+                           hipStream_t stream);
+
+// FP64 sums sum_j m_j / sqrt(|r_j - r_i|^2 + eps^2) (j = i included) into
+// part[s][3][i] for every source range s; *nsplit_out receives the count.
+size_t potential_partials_bytes(int64_t n);
+hipError_t launch_potential_partials(int prec, int64_t n, const void* x, const void* m, double eps,
+                                     double* part, int* nsplit_out, hipStream_t stream);
+
+// FP64 diagnostics into out[13] (device).
+size_t diag_workspace_bytes(int64_t n);
+hipError_t launch_diag(int prec, int64_t n, const void* x, const void* v, const void* m,
+                       double eps, double G, double* out, void* ws, hipStream_t stream);
+
+}  // namespace nb

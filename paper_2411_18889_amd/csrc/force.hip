@@ -1,0 +1,307 @@
+// Pair-force kernels of Eq. (1) (section "N-body simulation") for gfx950.
+//
+// Design (one launch = ni sinks against a range of sources):
+//  * a workgroup of BS threads owns BS*K sinks; each lane keeps K sinks in
+//    registers (sink k of lane t is i = group*BS*K + k*BS + t, so the SoA
+//    loads and stores of a wave are contiguous);
+//  * the sources are streamed in j-tiles of BS particles: every lane loads
+//    one source from the SoA arrays (coalesced), rounds it to the pair
+//    arithmetic type and stores it in LDS as (x, y, z, m); after a barrier
+//    every lane walks the whole tile, and every LDS read is a broadcast (all
+//    lanes read the same address, so no bank conflicts);
+//  * per pair: 3 subtractions, 3 FMAs for |d|^2 + eps^2 (eps^2 innermost, as
+//    the listing), one reciprocal square root, 3 multiplications for
+//    m_j / s^(3/2), 3 FMAs into the sums; no MFMA, since nothing here is a
+//    dense contraction;
+//  * small N: the source range is split over gridDim.y workgroups (j-split).
+//    Each writes its FP64 partial sums to the workspace and a second kernel
+//    adds them in a fixed order: no atomics, bitwise reproducible;
+//  * the sum over sources includes j = i, which adds exactly 0 to a_i (d = 0)
+//    and m_i / eps to the potential sum; that term is removed at the end.
+#include "common.h"
+
+namespace nb {
+
+namespace {
+
+constexpr int NQ = 4;  // partial quantities per sink: ax, ay, az, potential
+
+template <class Pol>
+struct ForceArgs {
+    using pos_t = typename Pol::pos_t;
+    using mass_t = typename Pol::mass_t;
+    using calc_t = typename Pol::calc_t;
+    const pos_t *xi, *yi, *zi;
+    const pos_t *xj, *yj, *zj;
+    const mass_t* mj;
+    const mass_t* mi;     // masses of the sinks (self set only, for the potential)
+    int ni, nj;
+    int jspan;            // sources per j-split range, a multiple of BS
+    calc_t eps2;
+    double G;
+    int self_pot;         // remove the j = i term m_i / eps from the potential
+    pos_t *ax, *ay, *az, *pot;  // final outputs (part == nullptr)
+    double* part;         // [nsplit][NQ][ni] FP64 partial sums, or nullptr
+};
+
+template <class Pol, bool POT>
+__device__ __forceinline__ void finish_sink(const ForceArgs<Pol>& a, int i, double sx, double sy,
+                                            double sz, double sp) {
+    using pos_t = typename Pol::pos_t;
+    using calc_t = typename Pol::calc_t;
+    a.ax[i] = pos_t(a.G * sx);
+    a.ay[i] = pos_t(a.G * sy);
+    a.az[i] = pos_t(a.G * sz);
+    if (POT) {
+        double self = 0.0;
+        if (a.self_pot) {
+            // the j = i term exactly as the pair loop added it
+            typename Pol::sum_t t;
+            t.init();
+            t.add_fma(calc_t(a.mi[i]), rsqrt_pair(a.eps2));
+            self = t.total();
+        }
+        a.pot[i] = pos_t(-a.G * (sp - self));
+    }
+}
+
+template <class Pol, int BS, int K, bool ACC, bool POT>
+__global__ __launch_bounds__(BS) void force_kernel(ForceArgs<Pol> a) {
+    using calc_t = typename Pol::calc_t;
+    using sum_t = typename Pol::sum_t;
+    using V4 = typename Vec4<calc_t>::type;
+    __shared__ V4 tile[BS];
+
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * (BS * K) + tid;
+    calc_t xi[K], yi[K], zi[K];
+    sum_t sx[K], sy[K], sz[K], sp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = i0 + k * BS;
+        const bool ok = i < a.ni;
+        xi[k] = ok ? calc_t(a.xi[i]) : calc_t(0);
+        yi[k] = ok ? calc_t(a.yi[i]) : calc_t(0);
+        zi[k] = ok ? calc_t(a.zi[i]) : calc_t(0);
+        sx[k].init(); sy[k].init(); sz[k].init(); sp[k].init();
+    }
+    const calc_t eps2 = a.eps2;
+    const int jbeg = blockIdx.y * a.jspan;
+    const int jend = min(a.nj, jbeg + a.jspan);
+
+    for (int jt = jbeg; jt < jend; jt += BS) {
+        const int j = jt + tid;
+        V4 p;
+        if (j < jend) {
+            p.x = calc_t(a.xj[j]);
+            p.y = calc_t(a.yj[j]);
+            p.z = calc_t(a.zj[j]);
+            p.w = calc_t(a.mj[j]);
+        } else {  // zero-mass padding: contributes exactly 0
+            p.x = calc_t(0); p.y = calc_t(0); p.z = calc_t(0); p.w = calc_t(0);
+        }
+        __syncthreads();
+        tile[tid] = p;
+        __syncthreads();
+#pragma unroll 8
+        for (int jj = 0; jj < BS; ++jj) {
+            const V4 q = tile[jj];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const calc_t dx = q.x - xi[k];
+                const calc_t dy = q.y - yi[k];
+                const calc_t dz = q.z - zi[k];
+                const calc_t s = fmat(dz, dz, fmat(dy, dy, fmat(dx, dx, eps2)));
+                const calc_t r = rsqrt_pair(s);
+                if (ACC) {
+                    calc_t w = r * (r * r);
+                    w = w * q.w;
+                    sx[k].add_fma(dx, w);
+                    sy[k].add_fma(dy, w);
+                    sz[k].add_fma(dz, w);
+                }
+                if (POT) sp[k].add_fma(q.w, r);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            sx[k].tile_end(); sy[k].tile_end(); sz[k].tile_end(); sp[k].tile_end();
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = i0 + k * BS;
+        if (i >= a.ni) continue;
+        if (a.part) {
+            double* q = a.part + (size_t)blockIdx.y * NQ * a.ni;
+            if (ACC) {
+                q[i] = sx[k].total();
+                q[(size_t)a.ni + i] = sy[k].total();
+                q[(size_t)2 * a.ni + i] = sz[k].total();
+            }
+            if (POT) q[(size_t)3 * a.ni + i] = sp[k].total();
+        } else if (ACC) {
+            finish_sink<Pol, POT>(a, i, sx[k].total(), sy[k].total(), sz[k].total(), sp[k].total());
+        }
+    }
+}
+
+// Adds the nsplit partial sums of every sink in split order, then finishes.
+template <class Pol, bool POT>
+__global__ __launch_bounds__(256) void force_reduce_kernel(ForceArgs<Pol> a, int nsplit) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.ni) return;
+    const size_t stride = (size_t)NQ * a.ni;
+    double sx = 0, sy = 0, sz = 0, sp = 0;
+    for (int s = 0; s < nsplit; ++s) {
+        const double* q = a.part + s * stride;
+        sx += q[i];
+        sy += q[(size_t)a.ni + i];
+        sz += q[(size_t)2 * a.ni + i];
+        if (POT) sp += q[(size_t)3 * a.ni + i];
+    }
+    finish_sink<Pol, POT>(a, i, sx, sy, sz, sp);
+}
+
+template <class Pol>
+ForceArgs<Pol> make_args(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
+                         double eps, double G, bool self_set, void* acc, void* pot) {
+    using pos_t = typename Pol::pos_t;
+    using mass_t = typename Pol::mass_t;
+    using calc_t = typename Pol::calc_t;
+    ForceArgs<Pol> a{};
+    const pos_t* pi = static_cast<const pos_t*>(xi);
+    const pos_t* pj = static_cast<const pos_t*>(xj);
+    a.xi = pi; a.yi = pi + ni; a.zi = pi + 2 * ni;
+    a.xj = pj; a.yj = pj + nj; a.zj = pj + 2 * nj;
+    a.mj = static_cast<const mass_t*>(mj);
+    a.mi = self_set ? a.mj : nullptr;
+    a.ni = (int)ni;
+    a.nj = (int)nj;
+    a.eps2 = calc_t(eps) * calc_t(eps);
+    a.G = G;
+    a.self_pot = (self_set && pot) ? 1 : 0;
+    pos_t* po = static_cast<pos_t*>(acc);
+    if (po) { a.ax = po; a.ay = po + ni; a.az = po + 2 * ni; }
+    a.pot = static_cast<pos_t*>(pot);
+    return a;
+}
+
+int split_span(int64_t nj, int split, int block) {
+    int64_t per = (nj + split - 1) / split;
+    per = (per + block - 1) / block * block;
+    return (int)per;
+}
+
+template <class Pol, bool ACC, bool POT, int BS, int K>
+hipError_t launch_shape(ForceArgs<Pol> a, int nsplit, hipStream_t stream) {
+    dim3 grid((a.ni + BS * K - 1) / (BS * K), nsplit);
+    hipLaunchKernelGGL((force_kernel<Pol, BS, K, ACC, POT>), grid, dim3(BS), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <class Pol, bool ACC, bool POT>
+hipError_t launch_any(const Shape& sh, ForceArgs<Pol> a, int nsplit, hipStream_t stream) {
+#define NB_FORCE_CASE(BSV, KV) \
+    if (sh.block == BSV && sh.ipl == KV) return launch_shape<Pol, ACC, POT, BSV, KV>(a, nsplit, stream);
+    NB_FORCE_CASE(64, 1) NB_FORCE_CASE(64, 2) NB_FORCE_CASE(64, 4)
+    NB_FORCE_CASE(128, 1) NB_FORCE_CASE(128, 2) NB_FORCE_CASE(128, 4)
+    NB_FORCE_CASE(256, 1) NB_FORCE_CASE(256, 2) NB_FORCE_CASE(256, 4)
+    NB_FORCE_CASE(512, 1) NB_FORCE_CASE(512, 2) NB_FORCE_CASE(512, 4)
+    NB_FORCE_CASE(1024, 1) NB_FORCE_CASE(1024, 2) NB_FORCE_CASE(1024, 4)
+#undef NB_FORCE_CASE
+    return hipErrorInvalidValue;
+}
+
+template <class Pol, bool ACC, bool POT>
+hipError_t run_force(const Shape& sh, ForceArgs<Pol> a, void* ws, bool partials_only,
+                     hipStream_t stream) {
+    const int span = split_span(a.nj, sh.split, sh.block);
+    const int nsplit = (a.nj + span - 1) / span;
+    a.jspan = span;
+    if (nsplit == 1 && !partials_only) {
+        a.part = nullptr;
+        return launch_any<Pol, ACC, POT>(sh, a, 1, stream);
+    }
+    a.part = static_cast<double*>(ws);
+    hipError_t e = launch_any<Pol, ACC, POT>(sh, a, nsplit, stream);
+    if (e != hipSuccess || partials_only) return e;
+    hipLaunchKernelGGL((force_reduce_kernel<Pol, POT>), dim3((a.ni + 255) / 256), dim3(256), 0,
+                       stream, a, nsplit);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool shape_supported(const Shape& s) {
+    const bool bs_ok = s.block == 64 || s.block == 128 || s.block == 256 || s.block == 512 ||
+                       s.block == 1024;
+    const bool k_ok = s.ipl == 1 || s.ipl == 2 || s.ipl == 4;
+    return bs_ok && k_ok && s.split >= 1 && s.split <= 256;
+}
+
+size_t force_partials_bytes(const Shape& s, int64_t ni) {
+    return (size_t)s.split * NQ * (size_t)ni * sizeof(double);
+}
+
+Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
+    Shape s{prec == NB_F64 ? 1 : 2, 256, 1};
+    // Aim for at least ~4 waves per SIMD (4096 waves on 256 CUs x 4 SIMDs);
+    // split the source range when the sinks alone cannot provide them, but
+    // keep every range at least two tiles long.
+    const int64_t groups = (ni + (int64_t)s.block * s.ipl - 1) / ((int64_t)s.block * s.ipl);
+    const int64_t waves = groups * (s.block / 64);
+    const int64_t want = 4096;
+    if (waves < want) {
+        int64_t split = (want + waves - 1) / waves;
+        const int64_t max_by_tiles = nj / (2 * (int64_t)s.block);
+        if (split > max_by_tiles) split = max_by_tiles;
+        if (split > 256) split = 256;
+        if (split < 1) split = 1;
+        s.split = (int)split;
+    }
+    return s;
+}
+
+hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi, int64_t nj,
+                        const void* xj, const void* mj, double eps, double G, bool self_set,
+                        void* acc, void* pot, void* ws, hipStream_t stream) {
+    hipError_t err = hipErrorInvalidValue;
+    dispatch_prec(prec, [&](auto tag) {
+        using Pol = decltype(tag);
+        auto a = make_args<Pol>(ni, xi, nj, xj, mj, eps, G, self_set, acc, pot);
+        err = pot ? run_force<Pol, true, true>(shape, a, ws, false, stream)
+                  : run_force<Pol, true, false>(shape, a, ws, false, stream);
+    });
+    return err;
+}
+
+// FP64 potential sums for the diagnostics: part[s][3][i] receives
+// sum_j m_j / sqrt(|r_j - r_i|^2 + eps^2) over source range s, j = i
+// included; positions and masses of the policy's storage types promoted to
+// FP64 exactly.
+hipError_t launch_potential_partials(int prec, int64_t n, const void* x, const void* m, double eps,
+                                     double* part, int* nsplit_out, hipStream_t stream) {
+    const Shape s = choose_force_shape(NB_F64, n, n);  // one sink per lane, 256 lanes
+    const int span = split_span(n, s.split, s.block);
+    *nsplit_out = (int)((n + span - 1) / span);
+    hipError_t err = hipErrorInvalidValue;
+    auto run = [&](auto tag) {
+        using Pol = decltype(tag);
+        auto a = make_args<Pol>(n, x, n, x, m, eps, 1.0, false, nullptr, nullptr);
+        a.jspan = span;
+        a.part = part;
+        err = launch_any<Pol, false, true>(s, a, *nsplit_out, stream);
+    };
+    if (prec == NB_F64) run(Policy<double, double, double, SumPlain<double>>{});
+    else if (prec == NB_F32) run(Policy<float, float, double, SumPlain<double>>{});
+    else run(Policy<double, float, double, SumPlain<double>>{});
+    return err;
+}
+
+size_t potential_partials_bytes(int64_t n) {
+    return force_partials_bytes(choose_force_shape(NB_F64, n, n), n);
+}
+
+}  // namespace nb

@@ -1,0 +1,382 @@
+// C ABI of libnbody (declared in include/nbody.h): argument checks, launch
+// shapes, and the host loops of the leapfrog and of its reverse walk.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+using namespace nb;
+
+thread_local int g_last_hip_error = 0;
+
+// ---- device-time profile (nbody_profile_begin / nbody_profile_end) --------
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+thread_local bool g_prof = false;
+thread_local std::vector<ProfRec> g_recs;
+thread_local std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pooled_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs f() (which enqueues work on s); while profiling, brackets it with events.
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F&& f) {
+    if (!g_prof) return f();
+    hipEvent_t a = pooled_event(), b = pooled_event();
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = f();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    g_recs.push_back({kind, a, b});
+    return e;
+}
+
+constexpr int64_t kMaxN = int64_t(1) << 30;
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+bool valid_prec(int prec) { return prec >= NB_F64 && prec <= NB_MIX_TILEC; }
+
+bool valid_eps(double eps, int prec) {
+    if (!isfinite(eps) || !(eps > 0.0)) return false;
+    // FP32 pair arithmetic needs eps^2 and eps^-3 to stay normal and finite
+    if (prec != NB_F64 && eps < 0x1p-40) return false;
+    if (prec == NB_F64 && eps < 1e-100) return false;
+    return true;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    if (!a || !b) return false;
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+// A gfx950 device must be current. The answer is cached per device id.
+int check_device() {
+    static std::atomic<int> cache[64];  // 0 unknown, 1 ok, 2 not gfx950
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0) {
+        (void)hipGetLastError();
+        return NB_ENODEV;
+    }
+    if (dev < 64 && cache[dev].load() == 1) return NB_OK;
+    if (dev < 64 && cache[dev].load() == 2) return NB_ENODEV;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return NB_ENODEV;
+    }
+    const bool ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev < 64) cache[dev].store(ok ? 1 : 2);
+    return ok ? NB_OK : NB_ENODEV;
+}
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return NB_OK;
+    g_last_hip_error = (int)e;
+    return NB_EDEVICE;
+}
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return NB_OK;
+    if (!ws || !aligned(ws, 256) || ws_bytes < need) return NB_EWORKSPACE;
+    return NB_OK;
+}
+
+size_t accel_ws(const Shape& s, int64_t ni) {
+    return s.split > 1 ? force_partials_bytes(s, ni) : 0;
+}
+
+hipError_t copy_state(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream);
+}
+
+int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
+                 double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
+                 void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_prec(prec)) return NB_EUNSUPPORTED;
+    if (ni < 1 || nj < 1 || ni > kMaxN || nj > kMaxN) return NB_EINVAL;
+    if (!valid_eps(eps, prec) || !isfinite(G)) return NB_EINVAL;
+    const size_t ps = pos_size(prec), ms = mass_size(prec);
+    if (!xi || !xj || !mj || !acc) return NB_EINVAL;
+    if (!aligned(xi, ps) || !aligned(xj, ps) || !aligned(mj, ms) || !aligned(acc, ps) ||
+        (pot && !aligned(pot, ps)))
+        return NB_EINVAL;
+    const bool self_set = (xi == xj);
+    if (self_set && ni != nj) return NB_EINVAL;
+    const size_t acc_b = 3 * (size_t)ni * ps;
+    if (overlaps(acc, acc_b, xi, 3 * (size_t)ni * ps) || overlaps(acc, acc_b, xj, 3 * (size_t)nj * ps) ||
+        overlaps(acc, acc_b, mj, (size_t)nj * ms))
+        return NB_EINVAL;
+    if (pot && (overlaps(pot, (size_t)ni * ps, acc, acc_b) ||
+                overlaps(pot, (size_t)ni * ps, xi, 3 * (size_t)ni * ps) ||
+                overlaps(pot, (size_t)ni * ps, xj, 3 * (size_t)nj * ps)))
+        return NB_EINVAL;
+    Shape sh = choose_force_shape(prec, ni, nj);
+    if (launch) {
+        if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
+        if (launch->block) sh.block = launch->block;
+        if (launch->split) sh.split = launch->split;
+        if (!shape_supported(sh)) return NB_EUNSUPPORTED;
+    }
+    int st = check_ws(ws, ws_bytes, accel_ws(sh, ni));
+    if (st != NB_OK) return st;
+    if ((st = check_device()) != NB_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return hip_status(timed(NB_PROF_FORCE, s, [&] {
+        return launch_force(prec, sh, ni, xi, nj, xj, mj, eps, G, self_set, acc, pot, ws, s);
+    }));
+}
+
+}  // namespace
+
+extern "C" {
+
+int nbody_accel(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj, double eps,
+                double G, int prec, void* acc, void* pot, void* ws, size_t ws_bytes, void* stream) {
+    return accel_common(ni, xi, nj, xj, mj, eps, G, prec, acc, pot, nullptr, ws, ws_bytes, stream);
+}
+
+int nbody_accel_ex(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
+                   double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
+                   void* ws, size_t ws_bytes, void* stream) {
+    return accel_common(ni, xi, nj, xj, mj, eps, G, prec, acc, pot, launch, ws, ws_bytes, stream);
+}
+
+int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps, double G,
+               double dt, int64_t nsteps, int prec, unsigned flags, void* ckpt, int64_t ckpt_every,
+               void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_prec(prec)) return NB_EUNSUPPORTED;
+    if (n < 1 || n > kMaxN || nsteps < 0) return NB_EINVAL;
+    if (!valid_eps(eps, prec) || !isfinite(G) || !isfinite(dt)) return NB_EINVAL;
+    if (flags & ~NB_ACC_VALID) return NB_EINVAL;
+    const size_t ps = pos_size(prec), ms = mass_size(prec);
+    if (!x || !v || !m || !acc) return NB_EINVAL;
+    if (!aligned(x, ps) || !aligned(v, ps) || !aligned(m, ms) || !aligned(acc, ps)) return NB_EINVAL;
+    const size_t vb = 3 * (size_t)n * ps;
+    if (overlaps(x, vb, v, vb) || overlaps(x, vb, acc, vb) || overlaps(v, vb, acc, vb) ||
+        overlaps(m, (size_t)n * ms, x, vb) || overlaps(m, (size_t)n * ms, v, vb) ||
+        overlaps(m, (size_t)n * ms, acc, vb))
+        return NB_EINVAL;
+    if (ckpt) {
+        if (ckpt_every < 1 || !aligned(ckpt, ps)) return NB_EINVAL;
+        const size_t cb = (size_t)(nsteps / ckpt_every + 1) * 3 * vb;
+        if (overlaps(ckpt, cb, x, vb) || overlaps(ckpt, cb, v, vb) || overlaps(ckpt, cb, acc, vb))
+            return NB_EINVAL;
+    }
+    const Shape sh = choose_force_shape(prec, n, n);
+    int st = check_ws(ws, ws_bytes, accel_ws(sh, n));
+    if (st != NB_OK) return st;
+    if ((st = check_device()) != NB_OK) return st;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double h = 0.5 * dt;
+    auto force = [&]() {
+        return timed(NB_PROF_FORCE, s, [&] {
+            return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, s);
+        });
+    };
+    auto store = [&](int64_t slot) -> hipError_t {
+        return timed(NB_PROF_COPY, s, [&] {
+            char* base = static_cast<char*>(ckpt) + (size_t)slot * 3 * vb;
+            hipError_t e = copy_state(base, x, vb, s);
+            if (e == hipSuccess) e = copy_state(base + vb, v, vb, s);
+            if (e == hipSuccess) e = copy_state(base + 2 * vb, acc, vb, s);
+            return e;
+        });
+    };
+    hipError_t e = hipSuccess;
+    if (!(flags & NB_ACC_VALID)) e = force();
+    if (e == hipSuccess && ckpt) e = store(0);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        e = timed(NB_PROF_UPDATE, s, [&] { return launch_kick_drift(prec, n, x, v, acc, h, dt, s); });
+        if (e == hipSuccess) e = force();
+        if (e == hipSuccess)
+            e = timed(NB_PROF_UPDATE, s, [&] { return launch_kick(prec, n, v, acc, h, s); });
+        if (e == hipSuccess && ckpt && (k + 1) % ckpt_every == 0) e = store((k + 1) / ckpt_every);
+    }
+    return hip_status(e);
+}
+
+int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, void* lam_x,
+                       void* lam_v, void* lam_m, double eps, double G, double dt, int64_t nsteps,
+                       int prec, unsigned flags, const void* ckpt, int64_t ckpt_every,
+                       int64_t step_end, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_prec(prec)) return NB_EUNSUPPORTED;
+    if (n < 1 || n > kMaxN || nsteps < 0) return NB_EINVAL;
+    if (!valid_eps(eps, prec) || !isfinite(G) || !isfinite(dt)) return NB_EINVAL;
+    if (flags & ~(NB_ADJ_ENTRY_HALF | NB_ADJ_EXIT_FULL)) return NB_EINVAL;
+    const size_t ps = pos_size(prec), ms = mass_size(prec);
+    if (!x || !v || !m || !acc || !lam_x || !lam_v || !lam_m) return NB_EINVAL;
+    if (!aligned(x, ps) || !aligned(v, ps) || !aligned(m, ms) || !aligned(acc, ps) ||
+        !aligned(lam_x, ps) || !aligned(lam_v, ps) || !aligned(lam_m, 8))
+        return NB_EINVAL;
+    const size_t vb = 3 * (size_t)n * ps;
+    const void* bufs[6] = {x, v, acc, lam_x, lam_v, lam_m};
+    const size_t sizes[6] = {vb, vb, vb, vb, vb, (size_t)n * 8};
+    for (int p = 0; p < 6; ++p) {
+        if (overlaps(bufs[p], sizes[p], m, (size_t)n * ms)) return NB_EINVAL;
+        for (int q = p + 1; q < 6; ++q)
+            if (overlaps(bufs[p], sizes[p], bufs[q], sizes[q])) return NB_EINVAL;
+    }
+    if (ckpt) {
+        if (ckpt_every < 1 || !aligned(ckpt, ps) || step_end < nsteps || step_end > kMaxN)
+            return NB_EINVAL;
+        const size_t cb = (size_t)(step_end / ckpt_every + 1) * 3 * vb;
+        for (int p = 0; p < 6; ++p)
+            if (overlaps(ckpt, cb, bufs[p], sizes[p])) return NB_EINVAL;
+    }
+    const Shape sh = choose_adjoint_shape(prec, n);
+    const size_t need = sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
+    int st = check_ws(ws, ws_bytes, need);
+    if (st != NB_OK) return st;
+    if ((st = check_device()) != NB_OK) return st;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double h = 0.5 * dt;
+    double* lm = static_cast<double*>(lam_m);
+    hipError_t e = hipSuccess;
+    auto fused = [&](double c, bool update_state) {
+        return timed(NB_PROF_ADJOINT, s, [&] {
+            return launch_adjoint(prec, sh, n, x, m, lam_v, eps, G, c, update_state, h, acc, v, lam_x,
+                                  lm, ws, s);
+        });
+    };
+    if (flags & NB_ADJ_ENTRY_HALF) e = fused(h, false);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        const int64_t step = step_end - 1 - k;  // absolute index of the state walked back to
+        const bool anchor = ckpt && (step % ckpt_every == 0);
+        if (anchor) {
+            e = timed(NB_PROF_UPDATE, s, [&] { return launch_axpy_pos(prec, 3 * n, lam_v, lam_x, dt, s); });
+            const char* base = static_cast<const char*>(ckpt) + (size_t)(step / ckpt_every) * 3 * vb;
+            if (e == hipSuccess)
+                e = timed(NB_PROF_COPY, s, [&] {
+                    hipError_t r = copy_state(x, base, vb, s);
+                    if (r == hipSuccess) r = copy_state(v, base + vb, vb, s);
+                    if (r == hipSuccess) r = copy_state(acc, base + 2 * vb, vb, s);
+                    return r;
+                });
+        } else {
+            e = timed(NB_PROF_UPDATE, s, [&] {
+                return launch_reverse_drift(prec, n, x, v, acc, lam_x, lam_v, h, dt, s);
+            });
+        }
+        const bool last = (k == nsteps - 1);
+        const double c = last ? ((flags & NB_ADJ_EXIT_FULL) ? dt : h) : dt;
+        if (e == hipSuccess) e = fused(c, !anchor);
+    }
+    return hip_status(e);
+}
+
+int nbody_diag(int64_t n, const void* x, const void* v, const void* m, double eps, double G,
+               int prec, double* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!valid_prec(prec)) return NB_EUNSUPPORTED;
+    if (n < 1 || n > kMaxN) return NB_EINVAL;
+    if (!valid_eps(eps, prec) || !isfinite(G)) return NB_EINVAL;
+    const size_t ps = pos_size(prec), ms = mass_size(prec);
+    if (!x || !v || !m || !out) return NB_EINVAL;
+    if (!aligned(x, ps) || !aligned(v, ps) || !aligned(m, ms) || !aligned(out, 8)) return NB_EINVAL;
+    int st = check_ws(ws, ws_bytes, diag_workspace_bytes(n));
+    if (st != NB_OK) return st;
+    if ((st = check_device()) != NB_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return hip_status(timed(NB_PROF_DIAG, s, [&] { return launch_diag(prec, n, x, v, m, eps, G, out, ws, s); }));
+}
+
+size_t nbody_workspace_size(int op, int64_t n, int prec) {
+    if (!valid_prec(prec) || n < 1 || n > kMaxN) return 0;
+    switch (op) {
+    case NB_OP_ACCEL:
+    case NB_OP_STEP:
+        return accel_ws(choose_force_shape(prec, n, n), n);
+    case NB_OP_ADJOINT: {
+        const Shape sh = choose_adjoint_shape(prec, n);
+        return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
+    }
+    case NB_OP_DIAG:
+        return diag_workspace_bytes(n);
+    default:
+        return 0;
+    }
+}
+
+const char* nbody_strerror(int status) {
+    switch (status) {
+    case NB_OK: return "success";
+    case NB_EINVAL: return "invalid argument";
+    case NB_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case NB_EUNSUPPORTED: return "unsupported precision, operation or launch shape";
+    case NB_ENODEV: return "no gfx950 device is current";
+    case NB_EDEVICE: return "a HIP call failed";
+    default: return "unknown status";
+    }
+}
+
+int nbody_last_hip_error(void) { return g_last_hip_error; }
+
+int nbody_profile_begin(void) {
+    g_prof = true;
+    return NB_OK;
+}
+
+int nbody_profile_end(nb_profile* out) {
+    nb_profile p;
+    memset(&p, 0, sizeof(p));
+    hipError_t err = hipSuccess;
+    for (const ProfRec& r : g_recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && err == hipSuccess) err = e;
+        if (r.kind >= 0 && r.kind < NB_PROF_KINDS) {
+            p.ms[r.kind] += ms;
+            p.calls[r.kind] += 1;
+        }
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    g_prof = false;
+    if (out) *out = p;
+    return hip_status(err);
+}
+
+int nbody_device_info(char* buf, size_t len) {
+    if (buf && len) buf[0] = 0;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return NB_ENODEV;
+    }
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return NB_ENODEV;
+    }
+    if (buf && len)
+        snprintf(buf, len, "%s %s, %d CUs, %d MHz, %.1f GiB, LDS %zu B/workgroup", p.name,
+                 p.gcnArchName, p.multiProcessorCount, p.clockRate / 1000,
+                 (double)p.totalGlobalMem / (1024.0 * 1024.0 * 1024.0), (size_t)p.sharedMemPerBlock);
+    return strncmp(p.gcnArchName, "gfx950", 6) == 0 ? NB_OK : NB_ENODEV;
+}
+
+}  // extern "C"

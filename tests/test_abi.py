@@ -1,0 +1,142 @@
+"""C-ABI contract of libnbody.so, checked without a GPU.
+
+The library must load, export every function include/nbody.h declares, and
+reject bad arguments before it makes any HIP call. The pointers below are
+fake (never dereferenced): every call here fails validation, except the
+no-device case, which only runs where no GPU is present.
+"""
+
+import ctypes
+import subprocess
+
+import pytest
+
+from paper_2411_18889_amd import _lib
+from paper_2411_18889_amd._lib import (NB_EINVAL, NB_ENODEV, NB_EUNSUPPORTED, NB_EWORKSPACE,
+                                       NB_OK, nb_launch)
+
+P = ctypes.c_void_p
+A = P(0x100000)  # fake, aligned device addresses; never reached
+B = P(0x200000)
+C = P(0x300000)
+D = P(0x400000)
+F64, F32, TILEC = 0, 1, 5
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _lib.declared_functions()
+    assert {"nbody_accel", "nbody_step", "nbody_step_adjoint", "nbody_diag"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for name in names:
+        assert name in exported, name
+        assert hasattr(L, name)
+
+
+def test_strerror(L):
+    texts = {_lib.strerror(s) for s in range(6)}
+    assert len(texts) == 6
+    assert _lib.strerror(NB_OK) == "success"
+    assert _lib.strerror(99) == "unknown status"
+
+
+def test_workspace_size(L):
+    assert L.nbody_workspace_size(9, 1000, F64) == 0        # unknown op
+    assert L.nbody_workspace_size(0, 1000, 17) == 0         # unknown precision
+    assert L.nbody_workspace_size(0, 0, F64) == 0           # n < 1
+    assert L.nbody_workspace_size(3, 1000, F64) > 0         # diagnostics always need some
+    assert L.nbody_workspace_size(0, 1 << 20, TILEC) == 0   # large N: no j-split
+    assert L.nbody_workspace_size(0, 4096, TILEC) > 0       # small N: split partials
+    assert L.nbody_workspace_size(2, 4096, TILEC) > 0
+
+
+def _accel(L, ni=64, xi=A, nj=64, xj=B, mj=C, eps=0.1, G=1.0, prec=F64, acc=D, pot=None,
+           ws=None, wsb=0):
+    return L.nbody_accel(ni, xi, nj, xj, mj, eps, G, prec, acc, pot, ws, wsb, None)
+
+
+def test_accel_validation(L):
+    assert _accel(L, ni=0) == NB_EINVAL
+    assert _accel(L, nj=0) == NB_EINVAL
+    assert _accel(L, ni=(1 << 30) + 1) == NB_EINVAL
+    assert _accel(L, eps=0.0) == NB_EINVAL
+    assert _accel(L, eps=-1.0) == NB_EINVAL
+    assert _accel(L, eps=float("nan")) == NB_EINVAL
+    assert _accel(L, eps=float("inf")) == NB_EINVAL
+    assert _accel(L, eps=2.0 ** -41, prec=F32) == NB_EINVAL   # FP32 needs eps >= 2^-40
+    assert _accel(L, G=float("inf")) == NB_EINVAL
+    assert _accel(L, xi=None) == NB_EINVAL
+    assert _accel(L, acc=None) == NB_EINVAL
+    assert _accel(L, xi=P(0x100004)) == NB_EINVAL              # misaligned for double
+    assert _accel(L, mj=P(0x300002), prec=F32) == NB_EINVAL     # misaligned for float
+    assert _accel(L, xi=A, xj=A, ni=64, nj=65) == NB_EINVAL     # same set, different counts
+    assert _accel(L, acc=P(0x100000 + 8)) == NB_EINVAL         # output overlaps the sinks
+    assert _accel(L, pot=P(0x400000 + 8)) == NB_EINVAL         # potential overlaps acc
+    assert _accel(L, prec=9) == NB_EUNSUPPORTED
+
+
+def test_accel_workspace_checked_before_device(L):
+    need = L.nbody_workspace_size(0, 4096, TILEC)
+    assert need > 0
+    args = dict(ni=4096, nj=4096, xi=P(0x1000000), xj=P(0x2000000), mj=P(0x3000000),
+                acc=P(0x4000000), prec=TILEC)
+    assert _accel(L, **args) == NB_EWORKSPACE
+    assert _accel(L, ws=P(0x5000000), wsb=need - 1, **args) == NB_EWORKSPACE
+    assert _accel(L, ws=P(0x5000000 + 128), wsb=need, **args) == NB_EWORKSPACE  # not 256-aligned
+
+
+def test_accel_ex_rejects_bad_shapes(L):
+    for shape in ((3, 256, 1), (2, 96, 1), (2, 256, 0x1000), (2, 2048, 1)):
+        ln = nb_launch(*shape)
+        st = L.nbody_accel_ex(64, A, 64, B, C, 0.1, 1.0, F64, D, None, ctypes.byref(ln), None,
+                              0, None)
+        assert st == NB_EUNSUPPORTED, shape
+
+
+def test_step_validation(L):
+    def step(n=64, x=A, v=B, m=C, acc=D, eps=0.1, dt=0.01, nsteps=1, prec=F64, flags=0,
+             ckpt=None, every=0):
+        return L.nbody_step(n, x, v, m, acc, eps, 1.0, dt, nsteps, prec, flags, ckpt, every,
+                            None, 0, None)
+    assert step(n=0) == NB_EINVAL
+    assert step(nsteps=-1) == NB_EINVAL
+    assert step(dt=float("nan")) == NB_EINVAL
+    assert step(flags=0x8) == NB_EINVAL
+    assert step(v=P(0x100000 + 64)) == NB_EINVAL                 # v overlaps x
+    assert step(ckpt=P(0x800000), every=0) == NB_EINVAL         # interval must be >= 1
+    assert step(ckpt=P(0x400000 + 64), every=1) == NB_EINVAL     # checkpoints overlap acc
+    assert step(prec=6) == NB_EUNSUPPORTED
+
+
+def test_adjoint_validation(L):
+    E, Fp, Gp = P(0x500000), P(0x600000), P(0x700000)
+
+    def adj(n=64, lam_m=Gp, flags=0, ckpt=None, every=0, step_end=0, nsteps=1):
+        return L.nbody_step_adjoint(n, A, B, C, D, E, Fp, lam_m, 0.1, 1.0, 0.01, nsteps, F64,
+                                    flags, ckpt, every, step_end, None, 0, None)
+    assert adj(n=0) == NB_EINVAL
+    assert adj(flags=0x4) == NB_EINVAL
+    assert adj(lam_m=P(0x500000 + 8)) == NB_EINVAL               # lam_m overlaps lam_x
+    assert adj(ckpt=P(0x900000), every=4, step_end=0, nsteps=1) == NB_EINVAL  # step_end < nsteps
+
+
+def test_diag_validation(L):
+    assert L.nbody_diag(0, A, B, C, 0.1, 1.0, F64, D, None, 0, None) == NB_EINVAL
+    assert L.nbody_diag(64, A, B, C, 0.1, 1.0, F64, None, None, 0, None) == NB_EINVAL
+    assert L.nbody_diag(64, A, B, C, 0.1, 1.0, F64, D, None, 0, None) == NB_EWORKSPACE
+
+
+def test_no_device_is_reported():
+    L = _lib.lib()
+    buf = ctypes.create_string_buffer(128)
+    if L.nbody_device_info(buf, 128) != NB_ENODEV:
+        pytest.skip("a GPU is present")
+    # valid arguments: the call gets as far as the device check and stops there
+    assert _accel(L) == NB_ENODEV
+    assert L.nbody_step(64, A, B, C, D, 0.1, 1.0, 0.01, 1, F64, 0, None, 0, None, 0, None) == NB_ENODEV

@@ -1,0 +1,115 @@
+"""GPU parity of the hand-written adjoint (fused adjoint pair kernel and the
+reverse KDK walk with checkpoints) against the oracle's FP64 reverse-mode
+gradient, which stores the whole trajectory and shares nothing with the
+GPU's reconstruction schedule."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2411_18889_amd as nb
+from nbody_inputs import plummer_sphere
+from tests.gpu_util import DEV, host, rel, to_dev
+
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n, seed):
+    x, v, m = plummer_sphere(n, seed)
+    m = m * np.random.default_rng(seed).uniform(0.5, 1.5, size=n)
+    y = x + 0.05 * np.random.default_rng(seed + 1).normal(size=x.shape)
+    return x, v, m, y
+
+
+def _oracle_grads(x, v, m, y, eps, dt, S):
+    n = x.shape[1]
+    xs, _, _, tx, _ = oracle.kdk(x, v, m, eps, dt, S, trajectory=True)
+    return oracle.adjoint(tx, m, eps, dt, 2.0 / n * (xs - y), np.zeros_like(v))
+
+
+def _gpu_grads(x, v, m, y, eps, dt, S, K, prec):
+    xd, vd, md = to_dev(x, v, m, prec)
+    xd.requires_grad_(True)
+    vd.requires_grad_(True)
+    md.requires_grad_(True)
+    xs, vs = nb.rollout(xd, vd, md, eps, dt, S, ckpt_every=K, prec=prec)
+    yd = torch.tensor(y, dtype=xs.dtype, device=DEV)
+    loss = ((xs - yd) ** 2).sum() / x.shape[1]
+    loss.backward()
+    return host(xd.grad), host(vd.grad), host(md.grad), (host(xd), host(vd), host(md))
+
+
+@pytest.mark.parametrize("n,S,K", [(64, 6, 2), (300, 12, 5), (1000, 9, 20)])
+def test_adjoint_f64_matches_oracle(n, S, K):
+    x, v, m, y = _problem(n, 60 + n)
+    eps, dt = 2.0 ** -5, 2.0 ** -7
+    gx, gv, gm, _ = _gpu_grads(x, v, m, y, eps, dt, S, K, "f64")
+    ox, ov, om = _oracle_grads(x, v, m, y, eps, dt, S)
+    assert rel(gx, ox) <= 1e-10
+    assert rel(gv, ov) <= 1e-10
+    assert rel(gm, om) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ("mix_tilec", "mix_acc64", "f32"))
+def test_adjoint_fp32_pairs_matches_oracle(prec):
+    n, S, K = 2048, 40, 20
+    x, v, m, y = _problem(n, 70)
+    eps, dt = 2.0 ** -7, 2.0 ** -8
+    gx, gv, gm, (x0, v0, m0) = _gpu_grads(x, v, m, y, eps, dt, S, K, prec)
+    ox, ov, om = _oracle_grads(x0, v0, m0, y, eps, dt, S)
+    errs = (rel(gx, ox), rel(gv, ov), rel(gm, om))
+    print(prec, "gradient rel err x0 %.3g v0 %.3g m %.3g" % errs)
+    assert max(errs) <= 1e-4
+
+
+def test_checkpoint_interval_invariance():
+    n, S = 512, 12
+    x, v, m, y = _problem(n, 80)
+    eps, dt = 2.0 ** -6, 2.0 ** -7
+    res = [_gpu_grads(x, v, m, y, eps, dt, S, K, "f64")[:3] for K in (1, 4, 5, 12, 100)]
+    for r in res[1:]:
+        for a, b in zip(r, res[0]):
+            assert rel(a, b) <= 1e-12
+
+
+def test_split_calls_equal_one_call():
+    """Three nbody_step_adjoint calls over consecutive spans (flags
+    ENTRY_HALF / EXIT_FULL) give the same gradient as the oracle."""
+    n, S = 256, 9
+    x, v, m, y = _problem(n, 81)
+    eps, dt = 2.0 ** -6, 2.0 ** -7
+    xd, vd, md = to_dev(x, v, m, "f64")
+    acc = torch.empty_like(xd)
+    nb.step(xd, vd, md, acc, eps, dt, S, prec="f64")
+    lx = (2.0 / n) * (xd - torch.tensor(y, device=DEV))
+    lv = torch.zeros_like(vd)
+    lm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    spans = [(3, True, True), (4, False, True), (2, False, False)]
+    for ns, entry, exit_full in spans:
+        nb.step_adjoint(xd, vd, md, acc, lx, lv, lm, eps, dt, ns, prec="f64",
+                        entry_half=entry, exit_full=exit_full)
+    ox, ov, om = _oracle_grads(x, v, m, y, eps, dt, S)
+    assert rel(host(lx), ox) <= 1e-10 and rel(host(lv), ov) <= 1e-10 and rel(host(lm), om) <= 1e-10
+    # and the state has been walked back to the initial one
+    assert float((xd - torch.tensor(x, device=DEV)).abs().max()) <= 1e-12
+
+
+def test_position_adjoint_sum_invariant_on_gpu():
+    n, S = 4096, 8
+    x, v, m, _ = _problem(n, 82)
+    eps, dt = 2.0 ** -7, 2.0 ** -8
+    xd, vd, md = to_dev(x, v, m, "mix_tilec")
+    acc = torch.empty_like(xd)
+    nb.step(xd, vd, md, acc, eps, dt, S, prec="mix_tilec")
+    rng = np.random.default_rng(3)
+    lx0 = rng.normal(size=(3, n))
+    lv0 = rng.normal(size=(3, n))
+    lx = torch.tensor(lx0, device=DEV)
+    lv = torch.tensor(lv0, device=DEV)
+    lm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    nb.step_adjoint(xd, vd, md, acc, lx, lv, lm, eps, dt, S, prec="mix_tilec", entry_half=True)
+    np.testing.assert_allclose(host(lx).sum(axis=1), lx0.sum(axis=1), rtol=0, atol=1e-6)
+    np.testing.assert_allclose(host(lv).sum(axis=1), lv0.sum(axis=1) + S * dt * lx0.sum(axis=1),
+                               rtol=0, atol=1e-6)
