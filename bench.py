@@ -47,7 +47,21 @@ def parse():
     ap.add_argument("--prec", default="mix_tilec")
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="sinks in the CPU-oracle baseline sample (0: skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one plain device-to-device copy of this many MiB (to "
+                         "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes}), flush=True)
 
 
 def main():
@@ -56,6 +70,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
 
     import numpy as np
     import torch

@@ -110,6 +110,10 @@ def test_position_adjoint_sum_invariant_on_gpu():
     lv = torch.tensor(lv0, device=DEV)
     lm = torch.zeros(n, dtype=torch.float64, device=DEV)
     nb.step_adjoint(xd, vd, md, acc, lx, lv, lm, eps, dt, S, prec="mix_tilec", entry_half=True)
-    np.testing.assert_allclose(host(lx).sum(axis=1), lx0.sum(axis=1), rtol=0, atol=1e-6)
-    np.testing.assert_allclose(host(lv).sum(axis=1), lv0.sum(axis=1) + S * dt * lx0.sum(axis=1),
-                               rtol=0, atol=1e-6)
+    # the position-adjoint updates cancel in the sum up to the FP32 rounding
+    # of the pair terms: bound the residual by 1e-5 of their total size
+    dlx = host(lx) - lx0
+    scale = np.abs(dlx).sum(axis=1)
+    assert np.all(np.abs(dlx.sum(axis=1)) <= 1e-5 * scale), (dlx.sum(axis=1), scale)
+    expect_lv = lv0.sum(axis=1) + S * dt * lx0.sum(axis=1)
+    assert np.all(np.abs(host(lv).sum(axis=1) - expect_lv) <= 1e-5 * S * dt * scale + 1e-9)
