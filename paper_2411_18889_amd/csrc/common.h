@@ -181,12 +181,6 @@ hipError_t launch_reverse_drift(int prec, int64_t n, void* x, void* v, const voi
 hipError_t launch_axpy_pos(int prec, int64_t n3, void* y, const void* xv, double a,
                            hipStream_t stream);
 
-// FP64 sums sum_j m_j / sqrt(|r_j - r_i|^2 + eps^2) (j = i included) into
-// part[s][3][i] for every source range s; *nsplit_out receives the count.
-size_t potential_partials_bytes(int64_t n);
-hipError_t launch_potential_partials(int prec, int64_t n, const void* x, const void* m, double eps,
-                                     double* part, int* nsplit_out, hipStream_t stream);
-
 // FP64 diagnostics into out[13] (device).
 size_t diag_workspace_bytes(int64_t n);
 hipError_t launch_diag(int prec, int64_t n, const void* x, const void* v, const void* m,

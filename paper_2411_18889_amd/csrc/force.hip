@@ -277,31 +277,4 @@ hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi
     return err;
 }
 
-// FP64 potential sums for the diagnostics: part[s][3][i] receives
-// sum_j m_j / sqrt(|r_j - r_i|^2 + eps^2) over source range s, j = i
-// included; positions and masses of the policy's storage types promoted to
-// FP64 exactly.
-hipError_t launch_potential_partials(int prec, int64_t n, const void* x, const void* m, double eps,
-                                     double* part, int* nsplit_out, hipStream_t stream) {
-    const Shape s = choose_force_shape(NB_F64, n, n);  // one sink per lane, 256 lanes
-    const int span = split_span(n, s.split, s.block);
-    *nsplit_out = (int)((n + span - 1) / span);
-    hipError_t err = hipErrorInvalidValue;
-    auto run = [&](auto tag) {
-        using Pol = decltype(tag);
-        auto a = make_args<Pol>(n, x, n, x, m, eps, 1.0, false, nullptr, nullptr);
-        a.jspan = span;
-        a.part = part;
-        err = launch_any<Pol, false, true>(s, a, *nsplit_out, stream);
-    };
-    if (prec == NB_F64) run(Policy<double, double, double, SumPlain<double>>{});
-    else if (prec == NB_F32) run(Policy<float, float, double, SumPlain<double>>{});
-    else run(Policy<double, float, double, SumPlain<double>>{});
-    return err;
-}
-
-size_t potential_partials_bytes(int64_t n) {
-    return force_partials_bytes(choose_force_shape(NB_F64, n, n), n);
-}
-
 }  // namespace nb
