@@ -53,6 +53,76 @@ def parse():
     return ap.parse_args()
 
 
+HBM_PEAK = 8.0e12                # MI355X HBM3E bandwidth, bytes/s
+DIFF_BYTES_PER_POINT = 8         # algorithmic: read f once, write fn once (FP32)
+DIFF_FLOP_PER_POINT = 13         # 7 multiplications + 6 additions per point
+
+
+def bench_diffusion(args):
+    """The 3-D diffusion stencil on an n^3 FP32 grid (workload diffusion-<n>):
+    one step = one explicit update of every point (ping-pong buffers)."""
+    import numpy as np
+    import torch
+
+    import paper_2411_18889_amd as nb
+    from paper_2411_18889_amd import _lib
+
+    n = int(args.workload.split("-")[1])
+    dev = torch.device("cuda:0")
+    print("device:", nb.device_info(), flush=True)
+    rng = np.random.Generator(np.random.PCG64(7))
+    f0 = rng.uniform(0.0, 1.0, size=(n, n, n)).astype(np.float32)
+    prm = dict(dx=1.0, dy=1.0, dz=1.0, dt=0.1, kappa=1.0)
+    a = torch.tensor(f0, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(max(1, args.warmup)):
+        nb.api.diffusion3d_step(a, out=b, **prm)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps) * 50
+    L = _lib.lib()
+    prof = _lib.nb_profile_t()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    _lib.check(L.nbody_profile_begin(), "nbody_profile_begin")
+    e0.record(stream)
+    src, dst = a, b
+    for _ in range(steps):
+        nb.api.diffusion3d_step(src, out=dst, **prm)
+        src, dst = dst, src
+    e1.record(stream)
+    torch.cuda.synchronize()
+    _lib.check(L.nbody_profile_end(ctypes.byref(prof)), "nbody_profile_end")
+    ms = e0.elapsed_time(e1) / steps
+    k_ms = prof.ms[2] / max(1, prof.calls[2])
+    pts = float(n) ** 3
+    cpu = None
+    if args.cpu_sample > 0:
+        import oracle
+        tc = time.time()
+        oracle.diffusion3d(f0.astype(np.float64), **prm)
+        tcpu = time.time() - tc
+        cpu = {"value": pts / tcpu / 1e9, "unit": "Gpoints/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": "one full FP64 step of the %d^3 grid (%.2f s)" % (n, tcpu)}
+    out = {
+        "metric": "3-D diffusion stencil throughput (points updated per second)",
+        "value": pts / (ms * 1e-3) / 1e9,
+        "unit": "Gpoints/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: seeded uniform field",
+        "config": {"workload": args.workload, "grid": [n, n, n], **prm},
+        "roofline": {"kernel": "diffusion_kernel", "bound": "hbm",
+                     "achieved": DIFF_BYTES_PER_POINT * pts / (k_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": DIFF_BYTES_PER_POINT * pts / (k_ms * 1e-3) / HBM_PEAK, "traffic": None,
+                     "bytes_per_point": DIFF_BYTES_PER_POINT, "avg_launch_ms": k_ms},
+        "gflops": DIFF_FLOP_PER_POINT * pts / (ms * 1e-3) / 1e9,
+        "paper_convention_GBps": 32 * pts / (ms * 1e-3) / 1e9,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_probe(mib):
     import torch
     nbytes = mib << 20
@@ -72,6 +142,9 @@ def main():
         sys.exit(2)
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
+        return
+    if args.workload.startswith("diffusion-"):
+        bench_diffusion(args)
         return
 
     import numpy as np

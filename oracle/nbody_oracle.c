@@ -28,6 +28,8 @@
  *   oracle_vjp,    the transposed Jacobian of Eq. (1) with respect to the
  *   oracle_jvp     positions and the masses applied to a vector, and the
  *                  Jacobian applied to a vector. Not in the paper.
+ *   oracle_diffusion3d  one explicit step of the 3-D diffusion equation
+ *                  (section "3D diffusion equation"), the paper's second demo.
  *   oracle_adjoint reverse-mode derivative of a KDK trajectory, one sub-step
  *                  (kick, drift, kick) at a time, read back from the stored
  *                  FP64 trajectory. Not in the paper.
@@ -275,6 +277,39 @@ void oracle_jvp(int64_t n, const double *x, const double *m, const double *u,
         ju[i] = G * acc[0];
         ju[n + i] = G * acc[1];
         ju[2 * n + i] = G * acc[2];
+    }
+}
+
+/*
+ * One explicit step of the 3-D diffusion equation du/dt = kappa lap(u)
+ * (section "3D diffusion equation"): on an nx x ny x nz grid stored with k
+ * fastest, index (i, j, k) -> k + nz (j + ny i), every point becomes
+ *   fn = cc f + ce f(i+1) + cw f(i-1) + cn f(j+1) + cs f(j-1) + ct f(k+1) + cb f(k-1)
+ * with ce = cw = kappa dt / dx^2, cn = cs = kappa dt / dy^2,
+ * ct = cb = kappa dt / dz^2, cc = 1 - (ce + cw + cn + cs + ct + cb), and a
+ * neighbour index outside the grid replaced by the nearest one inside.
+ */
+void oracle_diffusion3d(int64_t nx, int64_t ny, int64_t nz, double dx, double dy,
+                        double dz, double dt, double kappa, const double *f, double *fn)
+{
+    const double ce = kappa * dt / (dx * dx), cw = ce;
+    const double cn = kappa * dt / (dy * dy), cs = cn;
+    const double ct = kappa * dt / (dz * dz), cb = ct;
+    const double cc = 1.0 - (ce + cw + cn + cs + ct + cb);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nx; i++) {
+        const int64_t ip = i + 1 < nx ? i + 1 : nx - 1, im = i > 0 ? i - 1 : 0;
+        for (int64_t j = 0; j < ny; j++) {
+            const int64_t jp = j + 1 < ny ? j + 1 : ny - 1, jm = j > 0 ? j - 1 : 0;
+            for (int64_t k = 0; k < nz; k++) {
+                const int64_t kp = k + 1 < nz ? k + 1 : nz - 1, km = k > 0 ? k - 1 : 0;
+#define AT(a, b, c) f[(c) + nz * ((b) + ny * (a))]
+                fn[k + nz * (j + ny * i)] = cc * AT(i, j, k) + ce * AT(ip, j, k) + cw * AT(im, j, k) +
+                                            cn * AT(i, jp, k) + cs * AT(i, jm, k) + ct * AT(i, j, kp) +
+                                            cb * AT(i, j, km);
+#undef AT
+            }
+        }
     }
 }
 

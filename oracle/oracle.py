@@ -165,3 +165,20 @@ def adjoint(traj_x, m, eps, dt, lamx, lamv, G=1.0):
     lib.oracle_adjoint(n, S, _p(traj), _p(_f64(m, (n,))), float(eps), float(G), float(dt),
                        _p(lx), _p(lv), _p(lm))
     return lx, lv, lm
+
+
+def diffusion3d(f, dx, dy, dz, dt, kappa):
+    """One explicit step of the 3-D diffusion equation on the grid f (nx, ny, nz),
+    k fastest, clamped neighbours; returns fn (float64)."""
+    lib = _load()
+    if not hasattr(lib.oracle_diffusion3d, "_typed"):
+        i64, dbl = ctypes.c_int64, ctypes.c_double
+        lib.oracle_diffusion3d.argtypes = [i64, i64, i64, dbl, dbl, dbl, dbl, dbl, _D, _D]
+        lib.oracle_diffusion3d.restype = None
+        lib.oracle_diffusion3d._typed = True
+    g = _f64(f)
+    nx, ny, nz = g.shape
+    out = np.empty_like(g)
+    lib.oracle_diffusion3d(nx, ny, nz, float(dx), float(dy), float(dz), float(dt), float(kappa),
+                           _p(g), _p(out))
+    return out

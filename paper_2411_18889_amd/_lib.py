@@ -64,6 +64,8 @@ def lib():
     L.nbody_strerror.restype = ctypes.c_char_p
     L.nbody_last_hip_error.argtypes = []
     L.nbody_device_info.argtypes = [ctypes.c_char_p, sz]
+    L.diffusion3d_step.argtypes = [i64, i64, i64, dbl, dbl, dbl, dbl, dbl, vp, vp, vp]
+    L.diffusion3d_step.restype = ctypes.c_int
     L.nbody_profile_begin.argtypes = []
     L.nbody_profile_end.argtypes = [ctypes.POINTER(nb_profile_t)]
     for f in ("nbody_accel", "nbody_accel_ex", "nbody_step", "nbody_step_adjoint",
@@ -88,10 +90,14 @@ def check(status: int, what: str) -> None:
 
 
 def declared_functions() -> list:
-    """Names of the functions include/nbody.h declares."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nbody_\w+)\s*\(", text)))
+    """Names of the functions the headers under include/ declare."""
+    names = set()
+    inc = os.path.dirname(HEADER)
+    for h in sorted(os.listdir(inc)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
+            names.update(re.findall(r"\b((?:nbody|diffusion3d)_\w+)\s*\(", text))
+    return sorted(names)
 
 
 class nb_profile_t(ctypes.Structure):

@@ -167,6 +167,23 @@ def diag_dict(res) -> dict:
     return dict(zip(DIAG_FIELDS, res.tolist()))
 
 
+def diffusion3d_step(f, dx, dy, dz, dt, kappa, out=None, stream=None):
+    """One explicit step of the 3-D diffusion equation on the FP32 grid f
+    (nx, ny, nz), k fastest, clamped neighbours; returns fn (nx, ny, nz)."""
+    if not isinstance(f, torch.Tensor) or f.device.type != "cuda" or f.dtype != torch.float32 \
+            or f.dim() != 3 or not f.is_contiguous():
+        raise ValueError("f must be a contiguous float32 CUDA tensor of shape (nx, ny, nz)")
+    fn = torch.empty_like(f) if out is None else out
+    if fn.shape != f.shape or fn.dtype != f.dtype or not fn.is_contiguous() or fn.device != f.device:
+        raise ValueError("out must match f")
+    nx, ny, nz = f.shape
+    st = _lib.lib().diffusion3d_step(nx, ny, nz, float(dx), float(dy), float(dz), float(dt),
+                                     float(kappa), ctypes.c_void_p(f.data_ptr()),
+                                     ctypes.c_void_p(fn.data_ptr()), _stream(stream))
+    check(st, "diffusion3d_step")
+    return fn
+
+
 def device_info() -> str:
     buf = ctypes.create_string_buffer(256)
     st = _lib.lib().nbody_device_info(buf, 256)

@@ -181,6 +181,10 @@ hipError_t launch_reverse_drift(int prec, int64_t n, void* x, void* v, const voi
 hipError_t launch_axpy_pos(int prec, int64_t n3, void* y, const void* xv, double a,
                            hipStream_t stream);
 
+// One step of the 3-D diffusion stencil (FP32 grid, k fastest).
+hipError_t launch_diffusion3d(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
+                              double dt, double kappa, const float* f, float* fn, hipStream_t stream);
+
 // FP64 diagnostics into out[13] (device).
 size_t diag_workspace_bytes(int64_t n);
 hipError_t launch_diag(int prec, int64_t n, const void* x, const void* v, const void* m,

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.h"
+#include "diffusion3d.h"
 
 namespace {
 
@@ -300,6 +301,24 @@ int nbody_diag(int64_t n, const void* x, const void* v, const void* m, double ep
     if ((st = check_device()) != NB_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return hip_status(timed(NB_PROF_DIAG, s, [&] { return launch_diag(prec, n, x, v, m, eps, G, out, ws, s); }));
+}
+
+int diffusion3d_step(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
+                     double dt, double kappa, const float* f, float* fn, void* stream) {
+    if (nx < 1 || ny < 1 || nz < 1 || nx > (int64_t(1) << 21) || ny > 524280) return NB_EINVAL;
+    if (nx * ny > (int64_t(1) << 31) || nx * ny * nz > (int64_t(1) << 31) - 1) return NB_EINVAL;
+    for (double h : {dx, dy, dz})
+        if (!isfinite(h) || !(h > 0.0)) return NB_EINVAL;
+    if (!isfinite(dt) || !isfinite(kappa)) return NB_EINVAL;
+    if (!f || !fn || !aligned(f, 4) || !aligned(fn, 4)) return NB_EINVAL;
+    const size_t bytes = (size_t)(nx * ny * nz) * sizeof(float);
+    if (overlaps(f, bytes, fn, bytes)) return NB_EINVAL;
+    int st = check_device();
+    if (st != NB_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return hip_status(timed(NB_PROF_UPDATE, s, [&] {
+        return launch_diffusion3d(nx, ny, nz, dx, dy, dz, dt, kappa, f, fn, s);
+    }));
 }
 
 size_t nbody_workspace_size(int op, int64_t n, int prec) {

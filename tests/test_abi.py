@@ -140,3 +140,18 @@ def test_no_device_is_reported():
     # valid arguments: the call gets as far as the device check and stops there
     assert _accel(L) == NB_ENODEV
     assert L.nbody_step(64, A, B, C, D, 0.1, 1.0, 0.01, 1, F64, 0, None, 0, None, 0, None) == NB_ENODEV
+
+
+def test_diffusion_validation(L):
+    def step(nx=8, ny=8, nz=8, dx=1.0, dy=1.0, dz=1.0, dt=0.1, kappa=1.0, f=A, fn=B):
+        return L.diffusion3d_step(nx, ny, nz, dx, dy, dz, dt, kappa, f, fn, None)
+    assert step(nx=0) == NB_EINVAL
+    assert step(nx=(1 << 21) + 1) == NB_EINVAL
+    assert step(ny=524281) == NB_EINVAL
+    assert step(nx=2048, ny=2048, nz=1024) == NB_EINVAL   # more than 2^31 - 1 points
+    assert step(dx=0.0) == NB_EINVAL
+    assert step(dz=float("nan")) == NB_EINVAL
+    assert step(dt=float("inf")) == NB_EINVAL
+    assert step(f=None) == NB_EINVAL
+    assert step(fn=P(0x200002)) == NB_EINVAL                  # misaligned
+    assert step(fn=P(0x100000 + 64)) == NB_EINVAL              # overlaps f

@@ -18,7 +18,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "nbody_oracle.c")
 PIN_TESTS = ["tests/test_oracle_force.py", "tests/test_oracle_kdk.py",
-             "tests/test_oracle_adjoint.py"]
+             "tests/test_oracle_adjoint.py", "tests/test_oracle_diffusion.py"]
 
 MUTANTS = {
     "force_sign": ("const double dx = xj[j] - px;", "const double dx = px - xj[j];"),
@@ -44,6 +44,11 @@ MUTANTS = {
                            "g -= (li[0] * d[0] + li[1] * d[1] + li[2] * d[2]) / s32;"),
     "adjoint_wrong_point": ("oracle_vjp(n, x0, m, lamv, eps, G, jt, gt);", "oracle_vjp(n, x1, m, lamv, eps, G, jt, gt);"),
     "adjoint_drift_weight": ("lamv[k] += dt * lamx[k];", "lamv[k] += h * lamx[k];"),
+    "diffusion_axis_swap": ("const double ce = kappa * dt / (dx * dx), cw = ce;",
+                            "const double ce = kappa * dt / (dy * dy), cw = ce;"),
+    "diffusion_reflect": ("im = i > 0 ? i - 1 : 0;", "im = i > 0 ? i - 1 : (nx > 1 ? 1 : 0);"),
+    "diffusion_centre": ("const double cc = 1.0 - (ce + cw + cn + cs + ct + cb);",
+                         "const double cc = 1.0 - (ce + cw + cn + cs + ct);"),
 }
 
 
