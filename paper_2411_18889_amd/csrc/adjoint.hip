@@ -14,7 +14,8 @@
 // Per pair, with u = m_k lam_j - m_j lam_k and e = -3 s^-1 (d . u):
 //   T(d) u = s^-3/2 (u + e d)
 // i.e. 6 operations for u, 3 for d.u, 2 for e, 3 FMAs for u + e d and 3 for
-// the sum; plus 4 for the mass adjoint and the 12 + rsqrt of the force.
+// the sum; plus 4 for the mass adjoint and the 12 + rsqrt of the force:
+// 34 VALU + 1 rsqrt.
 //
 // Tiling, j-split and the fixed-order split reduction are as in the force
 // kernel; the LDS record of a source is (x, y, z, m) and (lam_x, lam_y,

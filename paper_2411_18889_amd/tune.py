@@ -1,0 +1,95 @@
+"""Launch-shape autotuner for the pair-force kernel.
+
+The paper picks the number of threads per block by a parameter survey on
+each machine (section "N-body simulation", NTHREADS); this tool does the same
+for the gfx950 kernel's three launch parameters: sinks per lane, workgroup
+size (= j-tile length) and j-split. For every (N, precision) it times
+``nbody_accel_ex`` on a seeded Plummer sphere for every supported shape,
+checks that each shape returns the same accelerations as the library's own
+choice (to 1e-5), and reports the fastest.
+
+    python -m paper_2411_18889_amd.tune --n 16384 65536 1048576 --prec mix_tilec f32
+
+Prints one JSON line per (N, precision): the best shape, its time, the
+library's current choice and its time.
+"""
+
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(n, prec, eps=2.0 ** -8, shapes=None, reps=None, seed=5):
+    import numpy as np
+    import torch
+
+    from . import api
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    from nbody_inputs import plummer_sphere
+
+    x, _, m = plummer_sphere(n, seed)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(x, dtype=api.pos_dtype(prec), device=dev)
+    M = torch.tensor(m, dtype=api.mass_dtype(prec), device=dev)
+    if reps is None:
+        reps = max(2, min(200, int(2e11 // (n * n))))
+    base = api.accel(X, M, eps, prec=prec)
+    t_lib = _time(lambda: api.accel(X, M, eps, prec=prec), reps)
+    if shapes is None:
+        splits = sorted({1, 2, 4, 8, 16, 32, 64, 128} | {max(1, min(256, (4096 * 64) // max(1, n)))})
+        shapes = list(itertools.product((1, 2, 4), (128, 256, 512, 1024), splits))
+    best = None
+    rows = []
+    for ipl, block, split in shapes:
+        if split > 1 and n // split < block:
+            continue
+        waves = -(-n // (ipl * block)) * (block // 64) * split
+        if split > 1 and waves > 65536:  # beyond 64 waves per SIMD a split only adds partials
+            continue
+        launch = {"i_per_lane": ipl, "block": block, "split": split}
+        a = api.accel(X, M, eps, prec=prec, launch=launch)
+        err = float(torch.linalg.norm(a - base) / torch.linalg.norm(base))
+        if err > 1e-5:
+            raise RuntimeError("shape %s disagrees with the default by %.3g" % (launch, err))
+        ms = _time(lambda: api.accel(X, M, eps, prec=prec, launch=launch), reps)
+        rows.append((ms, launch))
+        if best is None or ms < best[0]:
+            best = (ms, launch)
+    rows.sort(key=lambda r: r[0])
+    return {"n": n, "prec": prec, "best": best[1], "best_ms": best[0],
+            "best_gpairs_per_s": n * n / best[0] / 1e6, "library_ms": t_lib,
+            "library_gpairs_per_s": n * n / t_lib / 1e6,
+            "top5": [{"ms": ms, **ln} for ms, ln in rows[:5]]}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--n", type=int, nargs="+", default=[16384, 65536, 262144, 1048576])
+    ap.add_argument("--prec", nargs="+", default=["mix_tilec"])
+    args = ap.parse_args(argv)
+    for prec in args.prec:
+        for n in args.n:
+            print(json.dumps(tune(n, prec)), flush=True)
+
+
+if __name__ == "__main__":
+    main()

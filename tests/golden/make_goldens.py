@@ -10,9 +10,10 @@ Calls only the FP64 CPU oracle (oracle/) and the seeded input generator
       loss     L = (1/N) sum_i |x_200,i - y_i|^2 from the unperturbed state
       gx, gv, gm   dL/dx_0, dL/dv_0, dL/dm from the oracle's reverse-mode
                walk over the stored FP64 trajectory (float32 storage)
-      dirs_x, dirs_v, dirs_m   seeded random directions (unit 2-norm)
-      fd_x, fd_v, fd_m         central differences of L along them,
-               (L(p + h u) - L(p - h u)) / 2h with h = 1e-6, FP64 forward runs
+      fd_x, fd_v, fd_m   central differences (L(p + h u) - L(p - h u)) / 2h,
+               h = 1e-6, FP64 forward runs, along the directions
+               direction(block, k) (two per block; for the masses the step is
+               m * u, relative)
   energy_65536.txt   (workload fp32-65536) E(t) of the FP64 oracle run of
                100 steps from the FP32-rounded initial state, every step
 
@@ -35,6 +36,13 @@ from nbody_inputs import WORKLOADS, make_state, perturb_state, random_unit_vecto
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 H = 1e-6
+DIRECTION_SEEDS = {"x": 1001, "v": 1002, "m": 1003}
+
+
+def direction(block, k, n):
+    """The k-th seeded unit direction for block 'x', 'v' or 'm' of n particles."""
+    shape = (n,) if block == "m" else (3, n)
+    return random_unit_vectors(shape, DIRECTION_SEEDS[block] + 10 * k)
 
 
 def _loss(x0, v0, m, w, y):
@@ -58,10 +66,9 @@ def adjoint_golden():
     print("adjoint %.0f s" % (time.time() - t), flush=True)
     out = dict(y=y, loss=np.array(loss), gx=gx.astype(np.float32), gv=gv.astype(np.float32),
                gm=gm.astype(np.float32))
-    for name, shape, seed in (("x", (3, n), 1001), ("v", (3, n), 1002), ("m", (n,), 1003)):
-        dirs = np.stack([random_unit_vectors(shape, seed + 10 * k) for k in range(2)])
+    for name in "xvm":
         fd = []
-        for u in dirs:
+        for u in (direction(name, k, n) for k in range(2)):
             args_p = [x0, v0, m]
             args_m = [x0, v0, m]
             i = "xvm".index(name)
@@ -71,7 +78,6 @@ def adjoint_golden():
             args_m[i] = args_m[i] - H * step
             fd.append((_loss(*args_p, w, y) - _loss(*args_m, w, y)) / (2 * H))
             print("fd %s %.0f s: %.9e" % (name, time.time() - t, fd[-1]), flush=True)
-        out["dirs_" + name] = dirs
         out["fd_" + name] = np.array(fd)
     np.savez_compressed(os.path.join(HERE, "adjoint_16384.npz"), **out)
     print("wrote adjoint_16384.npz", flush=True)
