@@ -70,6 +70,92 @@ __global__ __launch_bounds__(TK * TJ) void diffusion_kernel(int nx, int ny, int 
     }
 }
 
+// Vector form for nz % 4 == 0: every lane owns 4 consecutive k points
+// (16-byte loads and stores), a wave covers 256 k points of one row, a
+// workgroup TJ4 rows; the plane two steps ahead is already in flight while
+// the current one is computed, so each wave keeps 2 KB of loads outstanding.
+// LDS row layout: [.., left halo at V_OFF - 1, 256 points at V_OFF.., right
+// halo] with V_OFF = 4 so each lane's 4 points are 16-byte aligned.
+constexpr int TK4 = 256;
+constexpr int TJ4 = 4;
+constexpr int CI4 = 32;
+constexpr int V_OFF = 4;
+constexpr int ROW = TK4 + 2 * V_OFF;
+
+__device__ __forceinline__ float4 load_row4(const float* __restrict__ f, int64_t row, int k0, int nz) {
+    // the 4 points k0..k0+3 of a row; lanes past the end of the row take the
+    // row's last point in every slot, which is what the clamped neighbour rule
+    // asks of the point before them
+    if (k0 < nz) return *reinterpret_cast<const float4*>(f + row + k0);
+    const float e = f[row + nz - 1];
+    return make_float4(e, e, e, e);
+}
+
+__global__ __launch_bounds__(64 * TJ4) void diffusion_kernel4(int nx, int ny, int nz, Coef c,
+                                                              const float* __restrict__ f,
+                                                              float* __restrict__ fn) {
+    __shared__ __align__(16) float pl[TJ4 + 2][ROW];
+    const int lane = threadIdx.x, ty = threadIdx.y;
+    const int k0 = blockIdx.x * TK4 + 4 * lane;
+    const int j = blockIdx.y * TJ4 + ty;
+    const int jc = min(j, ny - 1);
+    const int i0 = blockIdx.z * CI4, i1 = min(i0 + CI4, nx);
+    const int64_t plane = (int64_t)ny * nz;
+    const int64_t row = (int64_t)jc * nz;
+    const int64_t row_jm = (int64_t)max(j - 1, 0) * nz;
+    const int64_t row_jp = (int64_t)min(j + 1, ny - 1) * nz;
+    const int kl = blockIdx.x * TK4 - 1, kr = blockIdx.x * TK4 + TK4;  // tile halo points
+    const bool store = k0 < nz && j < ny;
+
+    float4 prev = load_row4(f, (int64_t)max(i0 - 1, 0) * plane + row, k0, nz);
+    float4 cur = load_row4(f, (int64_t)i0 * plane + row, k0, nz);
+    float4 next = load_row4(f, (int64_t)min(i0 + 1, nx - 1) * plane + row, k0, nz);
+    for (int i = i0; i < i1; ++i) {
+        const int64_t base = (int64_t)i * plane;
+        const float4 after = load_row4(f, (int64_t)min(i + 2, nx - 1) * plane + row, k0, nz);
+        __syncthreads();  // the previous plane has been read by every lane
+        *reinterpret_cast<float4*>(&pl[ty + 1][V_OFF + 4 * lane]) = cur;
+        if (lane == 0) pl[ty + 1][V_OFF - 1] = f[base + row + max(kl, 0)];
+        if (lane == 63) pl[ty + 1][V_OFF + TK4] = f[base + row + min(kr, nz - 1)];
+        if (ty == 0) {
+            *reinterpret_cast<float4*>(&pl[0][V_OFF + 4 * lane]) = load_row4(f, base + row_jm, k0, nz);
+        }
+        if (ty == TJ4 - 1) {
+            *reinterpret_cast<float4*>(&pl[TJ4 + 1][V_OFF + 4 * lane]) = load_row4(f, base + row_jp, k0, nz);
+        }
+        __syncthreads();
+        if (store) {
+            const float4 jp = *reinterpret_cast<const float4*>(&pl[ty + 2][V_OFF + 4 * lane]);
+            const float4 jm = *reinterpret_cast<const float4*>(&pl[ty][V_OFF + 4 * lane]);
+            const float km0 = pl[ty + 1][V_OFF + 4 * lane - 1];
+            const float kp3 = pl[ty + 1][V_OFF + 4 * lane + 4];
+            // the last point of the grid has itself as its k+1 neighbour
+            const float kp3c = (k0 + 4 < nz) ? kp3 : cur.w;
+            const float km0c = (k0 > 0) ? km0 : cur.x;
+            float4 r;
+#define NB_DIFF_POINT(OUT, C, N, P, JP, JM, KP, KM)                 \
+    {                                                               \
+        float t = c.cc * (C);                                       \
+        t = __builtin_fmaf(c.ce, (N), t);                           \
+        t = __builtin_fmaf(c.cw, (P), t);                           \
+        t = __builtin_fmaf(c.cn, (JP), t);                          \
+        t = __builtin_fmaf(c.cs, (JM), t);                          \
+        t = __builtin_fmaf(c.ct, (KP), t);                          \
+        OUT = __builtin_fmaf(c.cb, (KM), t);                        \
+    }
+            NB_DIFF_POINT(r.x, cur.x, next.x, prev.x, jp.x, jm.x, cur.y, km0c)
+            NB_DIFF_POINT(r.y, cur.y, next.y, prev.y, jp.y, jm.y, cur.z, cur.x)
+            NB_DIFF_POINT(r.z, cur.z, next.z, prev.z, jp.z, jm.z, cur.w, cur.y)
+            NB_DIFF_POINT(r.w, cur.w, next.w, prev.w, jp.w, jm.w, kp3c, cur.z)
+#undef NB_DIFF_POINT
+            *reinterpret_cast<float4*>(fn + base + row + k0) = r;
+        }
+        prev = cur;
+        cur = next;
+        next = after;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_diffusion3d(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
@@ -80,6 +166,15 @@ hipError_t launch_diffusion3d(int64_t nx, int64_t ny, int64_t nz, double dx, dou
     c.cn = c.cs = float(cn);
     c.ct = c.cb = float(ct);
     c.cc = float(1.0 - 2.0 * (ce + cn + ct));
+    const bool vec = nz % 4 == 0 && reinterpret_cast<uintptr_t>(f) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(fn) % 16 == 0 && (ny + TJ4 - 1) / TJ4 <= 65535;
+    if (vec) {
+        const dim3 grid4((unsigned)((nz + TK4 - 1) / TK4), (unsigned)((ny + TJ4 - 1) / TJ4),
+                         (unsigned)((nx + CI4 - 1) / CI4));
+        hipLaunchKernelGGL(diffusion_kernel4, grid4, dim3(64, TJ4), 0, stream, (int)nx, (int)ny, (int)nz,
+                           c, f, fn);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)((nz + TK - 1) / TK), (unsigned)((ny + TJ - 1) / TJ),
                     (unsigned)((nx + CI - 1) / CI));
     hipLaunchKernelGGL(diffusion_kernel, grid, dim3(TK, TJ), 0, stream, (int)nx, (int)ny, (int)nz, c, f,

@@ -246,7 +246,10 @@ size_t force_partials_bytes(const Shape& s, int64_t ni) {
 }
 
 Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
-    Shape s{prec == NB_F64 ? 1 : 2, 256, 1};
+    // FP32 pair arithmetic: 2 sinks per lane; 512-lane workgroups (512-source
+    // tiles, half the barriers per pair) once there are enough sinks to fill
+    // the chip with them (measured 2-3 % faster than 256 at N = 2^20).
+    Shape s{prec == NB_F64 ? 1 : 2, (prec != NB_F64 && ni >= (1 << 19)) ? 512 : 256, 1};
     // Aim for at least ~4 waves per SIMD (4096 waves on 256 CUs x 4 SIMDs);
     // split the source range when the sinks alone cannot provide them, but
     // keep every range at least two tiles long.
