@@ -210,18 +210,20 @@ hipError_t launch_any(const Shape& sh, AdjArgs<Pol> a, int nsplit, hipStream_t s
 }  // namespace
 
 Shape choose_adjoint_shape(int prec, int64_t n) {
-    Shape s{1, 256, 1};
+    // Measured on MI355X: one sink per lane (the fused pair body is long
+    // enough to hide latency on its own; two sinks per lane run 13 % slower),
+    // 512-lane workgroups from 2^19 sinks up, and a source split up to ~128K
+    // wavefronts (8 ranges at 2^20, 32 at 2^14), every range >= 2 tiles long.
     (void)prec;
+    Shape s{1, n >= (1 << 19) ? 512 : 256, 1};
     const int64_t waves = (n + s.block - 1) / s.block * (s.block / 64);
-    const int64_t want = 4096;
-    if (waves < want) {
-        int64_t split = (want + waves - 1) / waves;
-        const int64_t max_by_tiles = n / (2 * (int64_t)s.block);
-        if (split > max_by_tiles) split = max_by_tiles;
-        if (split > 256) split = 256;
-        if (split < 1) split = 1;
-        s.split = (int)split;
-    }
+    const int64_t want = 131072;
+    int64_t split = (want + waves - 1) / waves;
+    const int64_t max_by_tiles = n / (2 * (int64_t)s.block);
+    if (split > max_by_tiles) split = max_by_tiles;
+    if (split > 256) split = 256;
+    if (split < 1) split = 1;
+    s.split = (int)split;
     return s;
 }
 

@@ -246,24 +246,28 @@ size_t force_partials_bytes(const Shape& s, int64_t ni) {
 }
 
 Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
-    // FP32 pair arithmetic: 2 sinks per lane; 512-lane workgroups (512-source
-    // tiles, half the barriers per pair) once there are enough sinks to fill
-    // the chip with them (measured 2-3 % faster than 256 at N = 2^20).
-    Shape s{prec == NB_F64 ? 1 : 2, (prec != NB_F64 && ni >= (1 << 19)) ? 512 : 256, 1};
-    // Aim for at least ~4 waves per SIMD (4096 waves on 256 CUs x 4 SIMDs);
-    // split the source range when the sinks alone cannot provide them, but
-    // keep every range at least two tiles long.
+    // Measured on MI355X (launch-shape sweeps at N = 2^14 .. 2^20):
+    //  * FP32 pair arithmetic: 2 sinks per lane; 512-lane workgroups (fewer
+    //    barriers per pair) from 65536 sinks up, 128 below;
+    //  * many more workgroups than the chip holds at once balance the CUs
+    //    better even when one round would already fill every SIMD: split the
+    //    source range until there are ~64K wavefronts (8 ranges at 2^20,
+    //    32 at 2^18, 5-16 % faster), keeping every range >= 4 tiles long.
+    Shape s;
+    if (prec == NB_F64) {
+        s = Shape{1, 256, 1};
+    } else {
+        s = Shape{2, ni >= 65536 ? 512 : 128, 1};
+    }
     const int64_t groups = (ni + (int64_t)s.block * s.ipl - 1) / ((int64_t)s.block * s.ipl);
     const int64_t waves = groups * (s.block / 64);
-    const int64_t want = 4096;
-    if (waves < want) {
-        int64_t split = (want + waves - 1) / waves;
-        const int64_t max_by_tiles = nj / (2 * (int64_t)s.block);
-        if (split > max_by_tiles) split = max_by_tiles;
-        if (split > 256) split = 256;
-        if (split < 1) split = 1;
-        s.split = (int)split;
-    }
+    const int64_t want = 65536;
+    int64_t split = (want + waves - 1) / waves;
+    const int64_t max_by_tiles = nj / (4 * (int64_t)s.block);
+    if (split > max_by_tiles) split = max_by_tiles;
+    if (split > 256) split = 256;
+    if (split < 1) split = 1;
+    s.split = (int)split;
     return s;
 }
 
