@@ -117,3 +117,23 @@ def test_energy_drift_fp32_vs_fp64_short():
     print("energy drift over 20 steps:", drift)
     assert drift["mix_tilec"] <= 10 * drift["f64"] + 1e-6
     assert drift["f32"] <= 10 * drift["f64"] + 1e-5
+
+
+def test_resume_from_saved_state_is_bitwise(tmp_path):
+    """5 steps, save (x, v, a) with torch.save, reload, 5 more steps: bitwise
+    the same state as 10 steps in one call (the kernels are deterministic and
+    the saved acceleration is reused, not recomputed)."""
+    x, v, m = plummer_sphere(3000, 55)
+    eps, dt = 2.0 ** -7, 2.0 ** -8
+    for prec in ("mix_tilec", "f32", "f64"):
+        xa, va, ma = to_dev(x, v, m, prec)
+        xb, vb, mb = to_dev(x, v, m, prec)
+        aa, ab = torch.empty_like(xa), torch.empty_like(xb)
+        nb.step(xa, va, ma, aa, eps, dt, 10, prec=prec)
+        nb.step(xb, vb, mb, ab, eps, dt, 5, prec=prec)
+        path = tmp_path / ("state_%s.pt" % prec)
+        torch.save({"x": xb.cpu(), "v": vb.cpu(), "a": ab.cpu(), "step": 5}, path)
+        st = torch.load(path, weights_only=True)
+        xc, vc, ac = (st[k].to(DEV) for k in ("x", "v", "a"))
+        nb.step(xc, vc, mb, ac, eps, dt, 5, prec=prec, acc_valid=True)
+        assert torch.equal(xc, xa) and torch.equal(vc, va) and torch.equal(ac, aa), prec
