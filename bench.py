@@ -53,6 +53,36 @@ def parse():
     return ap.parse_args()
 
 
+CSRC = os.path.join(ROOT, "paper_2411_18889_amd", "csrc")
+KERNEL_SOURCES = {"force_kernel": ["common.h", "force.hip"],
+                  "adjoint_kernel": ["common.h", "adjoint.hip"],
+                  "diffusion_kernel4": ["common.h", "diffusion.hip"]}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def hbm_traffic(kernel, workload):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` on
+    `workload`, from the committed counter summary, or None when there is none
+    or the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)["%s@%s" % (kernel, workload)]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash(kernel):
+        return None
+    return rec["bytes_per_launch"]
+
+
 HBM_PEAK = 8.0e12                # MI355X HBM3E bandwidth, bytes/s
 DIFF_BYTES_PER_POINT = 8         # algorithmic: read f once, write fn once (FP32)
 DIFF_FLOP_PER_POINT = 13         # 7 multiplications + 6 additions per point
@@ -111,10 +141,11 @@ def bench_diffusion(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded uniform field",
         "config": {"workload": args.workload, "grid": [n, n, n], **prm},
-        "roofline": {"kernel": "diffusion_kernel", "bound": "hbm",
+        "roofline": {"kernel": "diffusion_kernel4", "bound": "hbm",
                      "achieved": DIFF_BYTES_PER_POINT * pts / (k_ms * 1e-3) / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": DIFF_BYTES_PER_POINT * pts / (k_ms * 1e-3) / HBM_PEAK, "traffic": None,
+                     "frac": DIFF_BYTES_PER_POINT * pts / (k_ms * 1e-3) / HBM_PEAK,
+                     "traffic": hbm_traffic("diffusion_kernel4", args.workload),
                      "bytes_per_point": DIFF_BYTES_PER_POINT, "avg_launch_ms": k_ms},
         "gflops": DIFF_FLOP_PER_POINT * pts / (ms * 1e-3) / 1e9,
         "paper_convention_GBps": 32 * pts / (ms * 1e-3) / 1e9,
@@ -239,16 +270,19 @@ def main():
     if dom == "adjoint":
         roof = {"kernel": "adjoint_kernel (fused force + J^T lam + G^T lam)", "bound": "alu",
                 "achieved": adj_tflops, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": adj_tflops * 1e12 / FP32_VECTOR_PEAK, "traffic": None,
+                "frac": adj_tflops * 1e12 / FP32_VECTOR_PEAK,
+                "traffic": hbm_traffic("adjoint_kernel", w.name),
                 "flop_per_pair": FLOP_PER_ADJOINT_PAIR, "avg_launch_ms": a_ms}
     else:
         roof = {"kernel": "force_kernel", "bound": "alu", "achieved": force_tflops,
                 "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK, "traffic": None,
+                "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK,
+                "traffic": hbm_traffic("force_kernel", w.name),
                 "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
     force_roof = {"kernel": "force_kernel", "bound": "alu", "achieved": force_tflops,
                   "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                   "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK,
+                  "traffic": hbm_traffic("force_kernel", w.name),
                   "frac_nonpacked_peak": force_tflops * 1e12 / FP32_NONPACKED_PEAK,
                   "ginteractions_per_s": float(n) * n / (f_ms * 1e-3) / 1e9,
                   "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}

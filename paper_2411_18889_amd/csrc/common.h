@@ -154,10 +154,12 @@ size_t force_partials_bytes(const Shape& s, int64_t ni);
 size_t adjoint_partials_bytes(const Shape& s, int64_t n);
 
 // Force: acc (and pot) of ni sinks. self_set: xi and xj are the same set.
+// kick_v (optional, 3 ni pos elements): also apply v <- v + kick_h * acc in
+// the epilogue, with acc as stored (the leapfrog's closing half-kick).
 hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi,
                         int64_t nj, const void* xj, const void* mj, double eps,
                         double G, bool self_set, void* acc, void* pot, void* ws,
-                        hipStream_t stream);
+                        hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0);
 
 // Fused adjoint pair pass at x with adjoint lam_v: computes a(x), J^T lam_v,
 // G^T lam_v and applies the epilogue
@@ -169,8 +171,6 @@ hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x
                           void* lam_x, double* lam_m, void* ws, hipStream_t stream);
 
 // O(N) leapfrog kernels over the 3n components of a pos array.
-hipError_t launch_kick(int prec, int64_t n, void* v, const void* acc, double h,
-                       hipStream_t stream);
 hipError_t launch_kick_drift(int prec, int64_t n, void* x, void* v, const void* acc,
                              double h, double dt, hipStream_t stream);
 // Reverse drift: lam_v += dt lam_x; v <- v - h acc; x <- x - dt v.

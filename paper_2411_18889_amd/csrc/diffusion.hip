@@ -77,7 +77,7 @@ __global__ __launch_bounds__(TK * TJ) void diffusion_kernel(int nx, int ny, int 
 // LDS row layout: [.., left halo at V_OFF - 1, 256 points at V_OFF.., right
 // halo] with V_OFF = 4 so each lane's 4 points are 16-byte aligned.
 constexpr int TK4 = 256;
-constexpr int TJ4 = 4;
+constexpr int TJ4 = 8;
 constexpr int CI4 = 32;
 constexpr int V_OFF = 4;
 constexpr int ROW = TK4 + 2 * V_OFF;
@@ -148,7 +148,10 @@ __global__ __launch_bounds__(64 * TJ4) void diffusion_kernel4(int nx, int ny, in
             NB_DIFF_POINT(r.z, cur.z, next.z, prev.z, jp.z, jm.z, cur.w, cur.y)
             NB_DIFF_POINT(r.w, cur.w, next.w, prev.w, jp.w, jm.w, kp3c, cur.z)
 #undef NB_DIFF_POINT
-            *reinterpret_cast<float4*>(fn + base + row + k0) = r;
+            // streaming store: fn is not read again by this step
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const v4f rv = {r.x, r.y, r.z, r.w};
+            __builtin_nontemporal_store(rv, reinterpret_cast<v4f*>(fn + base + row + k0));
         }
         prev = cur;
         cur = next;

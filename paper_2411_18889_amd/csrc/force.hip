@@ -41,6 +41,8 @@ struct ForceArgs {
     double G;
     int self_pot;         // remove the j = i term m_i / eps from the potential
     pos_t *ax, *ay, *az, *pot;  // final outputs (part == nullptr)
+    pos_t *vx, *vy, *vz;  // velocities to kick, or nullptr
+    double h;             // kick: v <- v + h a, with a as stored
     double* part;         // [nsplit][NQ][ni] FP64 partial sums, or nullptr
 };
 
@@ -49,9 +51,16 @@ __device__ __forceinline__ void finish_sink(const ForceArgs<Pol>& a, int i, doub
                                             double sz, double sp) {
     using pos_t = typename Pol::pos_t;
     using calc_t = typename Pol::calc_t;
-    a.ax[i] = pos_t(a.G * sx);
-    a.ay[i] = pos_t(a.G * sy);
-    a.az[i] = pos_t(a.G * sz);
+    const pos_t ax = pos_t(a.G * sx), ay = pos_t(a.G * sy), az = pos_t(a.G * sz);
+    a.ax[i] = ax;
+    a.ay[i] = ay;
+    a.az[i] = az;
+    if (a.vx) {  // the leapfrog's closing half-kick, same arithmetic as the kick kernel
+        const pos_t h = pos_t(a.h);
+        a.vx[i] = a.vx[i] + h * ax;
+        a.vy[i] = a.vy[i] + h * ay;
+        a.vz[i] = a.vz[i] + h * az;
+    }
     if (POT) {
         double self = 0.0;
         if (a.self_pot) {
@@ -273,11 +282,20 @@ Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
 
 hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi, int64_t nj,
                         const void* xj, const void* mj, double eps, double G, bool self_set,
-                        void* acc, void* pot, void* ws, hipStream_t stream) {
+                        void* acc, void* pot, void* ws, hipStream_t stream, void* kick_v,
+                        double kick_h) {
     hipError_t err = hipErrorInvalidValue;
     dispatch_prec(prec, [&](auto tag) {
         using Pol = decltype(tag);
+        using pos_t = typename Pol::pos_t;
         auto a = make_args<Pol>(ni, xi, nj, xj, mj, eps, G, self_set, acc, pot);
+        if (kick_v) {
+            pos_t* pv = static_cast<pos_t*>(kick_v);
+            a.vx = pv;
+            a.vy = pv + ni;
+            a.vz = pv + 2 * ni;
+            a.h = kick_h;
+        }
         err = pot ? run_force<Pol, true, true>(shape, a, ws, false, stream)
                   : run_force<Pol, true, false>(shape, a, ws, false, stream);
     });

@@ -1,8 +1,8 @@
-// O(N) kernels of the kick-drift-kick leapfrog and of its reverse walk.
-// Each thread updates components of the 3n-element SoA arrays; all accesses
-// are unit-stride and coalesced. These kernels are bound by HBM traffic, not
-// arithmetic: per component a kick moves 3 values (v in, a in, v out), a
-// kick-drift 5 and a reverse drift 7.
+// O(N) kernels of the kick-drift-kick leapfrog and of its reverse walk (the
+// closing half-kick of a step runs in the force kernel's epilogue). Each
+// thread updates components of the 3n-element SoA arrays; all accesses are
+// unit-stride and coalesced. These kernels are bound by HBM traffic, not
+// arithmetic: per component a kick-drift moves 5 values, a reverse drift 7.
 #include "common.h"
 
 namespace nb {
@@ -15,14 +15,6 @@ inline dim3 grid_for(int64_t count) {
     int64_t blocks = (count + TPB - 1) / TPB;
     if (blocks > 65536) blocks = 65536;  // grid-stride beyond this
     return dim3((unsigned)blocks);
-}
-
-template <typename T>
-__global__ __launch_bounds__(TPB) void kick_kernel(T* __restrict__ v, const T* __restrict__ a, T h,
-                                                   int64_t count) {
-    for (int64_t k = blockIdx.x * (int64_t)TPB + threadIdx.x; k < count;
-         k += (int64_t)gridDim.x * TPB)
-        v[k] = v[k] + h * a[k];
 }
 
 // v <- v + h a; x <- x + dt v
@@ -64,18 +56,6 @@ __global__ __launch_bounds__(TPB) void axpy_kernel(T* __restrict__ y, const T* _
 }
 
 }  // namespace
-
-hipError_t launch_kick(int prec, int64_t n, void* v, const void* acc, double h,
-                       hipStream_t stream) {
-    const int64_t c = 3 * n;
-    if (prec == NB_F32)
-        hipLaunchKernelGGL(kick_kernel<float>, grid_for(c), dim3(TPB), 0, stream,
-                           static_cast<float*>(v), static_cast<const float*>(acc), float(h), c);
-    else
-        hipLaunchKernelGGL(kick_kernel<double>, grid_for(c), dim3(TPB), 0, stream,
-                           static_cast<double*>(v), static_cast<const double*>(acc), h, c);
-    return hipGetLastError();
-}
 
 hipError_t launch_kick_drift(int prec, int64_t n, void* x, void* v, const void* acc, double h,
                              double dt, hipStream_t stream) {

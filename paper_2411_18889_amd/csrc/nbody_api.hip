@@ -191,9 +191,12 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double h = 0.5 * dt;
-    auto force = [&]() {
+    // force(kick): a <- a(x), and with kick the closing half-kick v <- v + h a
+    // in the same launch (the pair pass never reads v)
+    auto force = [&](bool kick) {
         return timed(NB_PROF_FORCE, s, [&] {
-            return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, s);
+            return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, s,
+                                kick ? v : nullptr, h);
         });
     };
     auto store = [&](int64_t slot) -> hipError_t {
@@ -206,13 +209,11 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
         });
     };
     hipError_t e = hipSuccess;
-    if (!(flags & NB_ACC_VALID)) e = force();
+    if (!(flags & NB_ACC_VALID)) e = force(false);
     if (e == hipSuccess && ckpt) e = store(0);
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
         e = timed(NB_PROF_UPDATE, s, [&] { return launch_kick_drift(prec, n, x, v, acc, h, dt, s); });
-        if (e == hipSuccess) e = force();
-        if (e == hipSuccess)
-            e = timed(NB_PROF_UPDATE, s, [&] { return launch_kick(prec, n, v, acc, h, s); });
+        if (e == hipSuccess) e = force(true);
         if (e == hipSuccess && ckpt && (k + 1) % ckpt_every == 0) e = store((k + 1) / ckpt_every);
     }
     return hip_status(e);
