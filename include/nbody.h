@@ -94,6 +94,8 @@ typedef enum nb_op {
 
 /* nbody_step() flags */
 #define NB_ACC_VALID 0x1u      /* acc already holds a(x) on entry            */
+#define NB_GRAPH 0x2u          /* replay the loop as an instantiated HIP graph
+                                  (see nbody_step)                            */
 
 /* nbody_step_adjoint() flags */
 #define NB_ADJ_ENTRY_HALF 0x1u /* apply the h-weighted position adjoint at the
@@ -163,11 +165,31 @@ int nbody_accel_ex(int64_t ni, const void *xi, int64_t nj, const void *xj,
  *              k * ckpt_every, slot 0 being the entry state
  *   ckpt_every checkpoint interval >= 1 (ignored when ckpt is NULL)
  *   ws         workspace of nbody_workspace_size(NB_OP_STEP, n, prec) bytes
+ *   flags      NB_ACC_VALID, NB_GRAPH
+ *
+ * NB_GRAPH: the 2 nsteps (+1) launches of the loop are recorded once into a
+ * HIP graph on a capture stream owned by the library, instantiated, and
+ * launched on `stream`; a later call with the same arguments (device,
+ * pointers, sizes, eps, G, dt, nsteps, prec, flags) launches the cached
+ * graph again, which saves the per-launch host cost when n is small. The
+ * results are bitwise those of the same call without NB_GRAPH. Up to 16
+ * graphs are kept per process (least recently used evicted, after its last
+ * launch has finished); instantiation allocates HIP runtime objects, held
+ * until nbody_graph_cache_clear() or process end. The flag is ignored while
+ * a profile is being taken (nbody_profile_begin) and when `stream` is itself
+ * being captured (the launches then go into the caller's graph).
  */
 int nbody_step(int64_t n, void *x, void *v, const void *m, void *acc,
                double eps, double G, double dt, int64_t nsteps, int prec,
                unsigned flags, void *ckpt, int64_t ckpt_every, void *ws,
                size_t ws_bytes, void *stream);
+
+/*
+ * nbody_graph_cache_clear -- waits for the last launch of every graph that
+ * nbody_step cached for NB_GRAPH and frees them. NB_EDEVICE if a HIP call
+ * failed (the cache is emptied either way).
+ */
+int nbody_graph_cache_clear(void);
 
 /*
  * nbody_step_adjoint -- reverse-mode derivative of nbody_step, walking

@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nbody.h")
 NB_OK, NB_EINVAL, NB_EWORKSPACE, NB_EUNSUPPORTED, NB_ENODEV, NB_EDEVICE = range(6)
 NB_OP_ACCEL, NB_OP_STEP, NB_OP_ADJOINT, NB_OP_DIAG = range(4)
 NB_ACC_VALID = 0x1
+NB_GRAPH = 0x2
 NB_ADJ_ENTRY_HALF = 0x1
 NB_ADJ_EXIT_FULL = 0x2
 
@@ -68,9 +69,10 @@ def lib():
     L.diffusion3d_step.restype = ctypes.c_int
     L.nbody_profile_begin.argtypes = []
     L.nbody_profile_end.argtypes = [ctypes.POINTER(nb_profile_t)]
+    L.nbody_graph_cache_clear.argtypes = []
     for f in ("nbody_accel", "nbody_accel_ex", "nbody_step", "nbody_step_adjoint",
               "nbody_diag", "nbody_last_hip_error", "nbody_device_info",
-              "nbody_profile_begin", "nbody_profile_end"):
+              "nbody_profile_begin", "nbody_profile_end", "nbody_graph_cache_clear"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

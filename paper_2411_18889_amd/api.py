@@ -98,10 +98,13 @@ def accel(x, m, eps, G=1.0, prec="mix_tilec", xj=None, potential=False, launch=N
 
 
 def step(x, v, m, acc, eps, dt, nsteps, G=1.0, prec="mix_tilec", acc_valid=False,
-         ckpt=None, ckpt_every=0, stream=None):
+         ckpt=None, ckpt_every=0, stream=None, graph=False, workspace=None):
     """nsteps KDK steps in place on x, v, acc. ckpt: optional tensor of
     (nsteps // ckpt_every + 1, 9 n) pos elements receiving (x, v, acc) every
-    ckpt_every steps."""
+    ckpt_every steps. graph=True replays the loop as a cached HIP graph
+    (NB_GRAPH); pass the same `workspace` (uint8 tensor of at least
+    workspace_size(NB_OP_STEP, n, prec) bytes) on every call so that the
+    cached graph is found again."""
     p = _prec(prec)
     pdt, mdt = pos_dtype(prec), mass_dtype(prec)
     n = x.shape[1]
@@ -112,10 +115,16 @@ def step(x, v, m, acc, eps, dt, nsteps, G=1.0, prec="mix_tilec", acc_valid=False
         pc = _vec(ckpt, "ckpt", 9 * n, pdt, rows=slots)
     else:
         pc = ctypes.c_void_p(0)
-    ws, pws, nws = _workspace(_lib.NB_OP_STEP, n, prec, x.device)
+    if workspace is not None:
+        need = workspace_size(_lib.NB_OP_STEP, n, prec)
+        if workspace.dtype != torch.uint8 or not workspace.is_contiguous() or workspace.numel() < need:
+            raise ValueError("workspace: contiguous uint8 tensor of >= %d bytes" % need)
+        pws, nws = ctypes.c_void_p(workspace.data_ptr() if need else 0), workspace.numel()
+    else:
+        ws, pws, nws = _workspace(_lib.NB_OP_STEP, n, prec, x.device)
+    flags = (_lib.NB_ACC_VALID if acc_valid else 0) | (_lib.NB_GRAPH if graph else 0)
     st = _lib.lib().nbody_step(n, *args, float(eps), float(G), float(dt), int(nsteps), p,
-                               _lib.NB_ACC_VALID if acc_valid else 0, pc, int(ckpt_every),
-                               pws, nws, _stream(stream))
+                               flags, pc, int(ckpt_every), pws, nws, _stream(stream))
     check(st, "nbody_step")
 
 
@@ -189,3 +198,9 @@ def device_info() -> str:
     st = _lib.lib().nbody_device_info(buf, 256)
     check(st, "nbody_device_info")
     return buf.value.decode()
+
+
+def graph_cache_clear():
+    """Free the HIP graphs that step(graph=True) cached (after their last
+    launches finish)."""
+    check(_lib.lib().nbody_graph_cache_clear(), "nbody_graph_cache_clear")

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -111,6 +112,93 @@ hipError_t copy_state(void* dst, const void* src, size_t bytes, hipStream_t stre
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, stream);
 }
 
+// ---- instantiated leapfrog graphs (nbody_step with NB_GRAPH) ---------------
+// A graph is recorded on a library-owned capture stream of the device (so the
+// caller's stream may be the null stream), instantiated once per distinct
+// argument set, and replayed with hipGraphLaunch on the caller's stream.
+struct StepKey {
+    int dev;
+    int prec;
+    unsigned flags;
+    int64_t n, nsteps, ckpt_every;
+    const void *x, *v, *m, *acc, *ckpt, *ws;
+    size_t ws_bytes;
+    double eps, G, dt;
+};
+
+struct GraphEntry {
+    StepKey key;
+    hipGraphExec_t exec;
+    hipEvent_t done;  // recorded after the entry's latest launch
+    uint64_t used;
+};
+
+constexpr size_t kGraphCacheMax = 16;
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+hipStream_t g_capture_stream[64] = {};
+
+bool same_key(const StepKey& a, const StepKey& b) { return memcmp(&a, &b, sizeof(StepKey)) == 0; }
+
+// Waits for the entry's last launch, then frees it. Caller holds g_graph_mu.
+hipError_t release_graph(GraphEntry& g) {
+    hipError_t e = hipEventSynchronize(g.done);
+    hipError_t e2 = hipGraphExecDestroy(g.exec);
+    hipError_t e3 = hipEventDestroy(g.done);
+    return e != hipSuccess ? e : (e2 != hipSuccess ? e2 : e3);
+}
+
+// Replays the graph of `key` on s, recording it first with enqueue(q) on the
+// capture stream q if it is not cached.
+template <class F>
+hipError_t graph_launch(const StepKey& key, hipStream_t s, F&& enqueue) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    GraphEntry* hit = nullptr;
+    for (GraphEntry& g : g_graphs)
+        if (same_key(g.key, key)) hit = &g;
+    if (!hit) {
+        if (key.dev < 0 || key.dev >= 64) return hipErrorInvalidDevice;
+        hipError_t e = hipSuccess;
+        if (g_graphs.size() >= kGraphCacheMax) {
+            size_t lru = 0;
+            for (size_t k = 1; k < g_graphs.size(); ++k)
+                if (g_graphs[k].used < g_graphs[lru].used) lru = k;
+            e = release_graph(g_graphs[lru]);
+            g_graphs.erase(g_graphs.begin() + (ptrdiff_t)lru);
+            if (e != hipSuccess) return e;
+        }
+        hipStream_t& q = g_capture_stream[key.dev];
+        if (!q && (e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess) {
+            q = nullptr;
+            return e;
+        }
+        if ((e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+        const hipError_t recorded = enqueue(q);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(q, &graph);
+        if (recorded != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return recorded != hipSuccess ? recorded : e;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        hipEvent_t done = nullptr;
+        if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            return e;
+        }
+        g_graphs.push_back(GraphEntry{key, exec, done, 0});
+        hit = &g_graphs.back();
+    }
+    hit->used = ++g_graph_clock;
+    hipError_t e = hipGraphLaunch(hit->exec, s);
+    if (e == hipSuccess) e = hipEventRecord(hit->done, s);
+    return e;
+}
+
 int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
                  double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
                  void* ws, size_t ws_bytes, void* stream) {
@@ -169,7 +257,7 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
     if (!valid_prec(prec)) return NB_EUNSUPPORTED;
     if (n < 1 || n > kMaxN || nsteps < 0) return NB_EINVAL;
     if (!valid_eps(eps, prec) || !isfinite(G) || !isfinite(dt)) return NB_EINVAL;
-    if (flags & ~NB_ACC_VALID) return NB_EINVAL;
+    if (flags & ~(NB_ACC_VALID | NB_GRAPH)) return NB_EINVAL;
     const size_t ps = pos_size(prec), ms = mass_size(prec);
     if (!x || !v || !m || !acc) return NB_EINVAL;
     if (!aligned(x, ps) || !aligned(v, ps) || !aligned(m, ms) || !aligned(acc, ps)) return NB_EINVAL;
@@ -191,32 +279,76 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     const double h = 0.5 * dt;
-    // force(kick): a <- a(x), and with kick the closing half-kick v <- v + h a
-    // in the same launch (the pair pass never reads v)
-    auto force = [&](bool kick) {
-        return timed(NB_PROF_FORCE, s, [&] {
-            return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, s,
-                                kick ? v : nullptr, h);
-        });
+    // Enqueues the whole loop on q.
+    auto enqueue = [&](hipStream_t q) -> hipError_t {
+        // force(kick): a <- a(x), and with kick the closing half-kick
+        // v <- v + h a in the same launch (the pair pass never reads v)
+        auto force = [&](bool kick) {
+            return timed(NB_PROF_FORCE, q, [&] {
+                return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, q,
+                                    kick ? v : nullptr, h);
+            });
+        };
+        auto store = [&](int64_t slot) -> hipError_t {
+            return timed(NB_PROF_COPY, q, [&] {
+                char* base = static_cast<char*>(ckpt) + (size_t)slot * 3 * vb;
+                hipError_t e = copy_state(base, x, vb, q);
+                if (e == hipSuccess) e = copy_state(base + vb, v, vb, q);
+                if (e == hipSuccess) e = copy_state(base + 2 * vb, acc, vb, q);
+                return e;
+            });
+        };
+        hipError_t e = hipSuccess;
+        if (!(flags & NB_ACC_VALID)) e = force(false);
+        if (e == hipSuccess && ckpt) e = store(0);
+        for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+            e = timed(NB_PROF_UPDATE, q, [&] { return launch_kick_drift(prec, n, x, v, acc, h, dt, q); });
+            if (e == hipSuccess) e = force(true);
+            if (e == hipSuccess && ckpt && (k + 1) % ckpt_every == 0) e = store((k + 1) / ckpt_every);
+        }
+        return e;
     };
-    auto store = [&](int64_t slot) -> hipError_t {
-        return timed(NB_PROF_COPY, s, [&] {
-            char* base = static_cast<char*>(ckpt) + (size_t)slot * 3 * vb;
-            hipError_t e = copy_state(base, x, vb, s);
-            if (e == hipSuccess) e = copy_state(base + vb, v, vb, s);
-            if (e == hipSuccess) e = copy_state(base + 2 * vb, acc, vb, s);
-            return e;
-        });
-    };
-    hipError_t e = hipSuccess;
-    if (!(flags & NB_ACC_VALID)) e = force(false);
-    if (e == hipSuccess && ckpt) e = store(0);
-    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
-        e = timed(NB_PROF_UPDATE, s, [&] { return launch_kick_drift(prec, n, x, v, acc, h, dt, s); });
-        if (e == hipSuccess) e = force(true);
-        if (e == hipSuccess && ckpt && (k + 1) % ckpt_every == 0) e = store((k + 1) / ckpt_every);
+    // NB_GRAPH: replay a cached graph of the loop, unless a profile is being
+    // taken (it times each launch group) or s is itself being captured (the
+    // launches then go into the caller's graph)
+    if ((flags & NB_GRAPH) && !g_prof) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(s, &cap);
+        if (e != hipSuccess) return hip_status(e);
+        if (cap == hipStreamCaptureStatusNone) {
+            StepKey key;
+            memset(&key, 0, sizeof(key));
+            if ((e = hipGetDevice(&key.dev)) != hipSuccess) return hip_status(e);
+            key.prec = prec;
+            key.flags = flags;
+            key.n = n;
+            key.nsteps = nsteps;
+            key.ckpt_every = ckpt ? ckpt_every : 0;
+            key.x = x;
+            key.v = v;
+            key.m = m;
+            key.acc = acc;
+            key.ckpt = ckpt;
+            key.ws = ws;
+            key.ws_bytes = ws_bytes;
+            key.eps = eps;
+            key.G = G;
+            key.dt = dt;
+            return hip_status(graph_launch(key, s, enqueue));
+        }
     }
-    return hip_status(e);
+    return hip_status(enqueue(s));
+}
+
+int nbody_graph_cache_clear(void) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    hipError_t err = hipSuccess;
+    for (GraphEntry& g : g_graphs) {
+        hipError_t e = release_graph(g);
+        if (err == hipSuccess) err = e;
+    }
+    g_graphs.clear();
+    return hip_status(err);
 }
 
 int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, void* lam_x,

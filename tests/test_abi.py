@@ -109,6 +109,7 @@ def test_step_validation(L):
     assert step(nsteps=-1) == NB_EINVAL
     assert step(dt=float("nan")) == NB_EINVAL
     assert step(flags=0x8) == NB_EINVAL
+    assert step(flags=0x4 | 0x2) == NB_EINVAL                    # unknown bit beside NB_GRAPH
     assert step(v=P(0x100000 + 64)) == NB_EINVAL                 # v overlaps x
     assert step(ckpt=P(0x800000), every=0) == NB_EINVAL         # interval must be >= 1
     assert step(ckpt=P(0x400000 + 64), every=1) == NB_EINVAL     # checkpoints overlap acc
@@ -141,6 +142,7 @@ def test_no_device_is_reported():
     # valid arguments: the call gets as far as the device check and stops there
     assert _accel(L) == NB_ENODEV
     assert L.nbody_step(64, A, B, C, D, 0.1, 1.0, 0.01, 1, F64, 0, None, 0, None, 0, None) == NB_ENODEV
+    assert L.nbody_step(64, A, B, C, D, 0.1, 1.0, 0.01, 1, F64, 0x2, None, 0, None, 0, None) == NB_ENODEV
 
 
 def test_diffusion_validation(L):

@@ -52,7 +52,23 @@ def test_adjoint_f64_matches_oracle(n, S, K):
     assert rel(gm, om) <= 1e-10
 
 
-@pytest.mark.parametrize("prec", ("mix_tilec", "mix_acc64", "f32"))
+def test_gradcheck_f64_rollout():
+    """torch.autograd.gradcheck of the FP64 rollout: the hand-written adjoint
+    against central differences of the GPU's own forward."""
+    n, S = 8, 3
+    x, v, m, _ = _problem(n, 83)
+    xd, vd, md = to_dev(x, v, m, "f64")
+    for t in (xd, vd, md):
+        t.requires_grad_(True)
+
+    def f(a, b, c):
+        xs, vs = nb.rollout(a, b, c, 2.0 ** -3, 2.0 ** -5, S, ckpt_every=2, prec="f64")
+        return xs, vs
+
+    assert torch.autograd.gradcheck(f, (xd, vd, md), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ("mix_tilec", "mix_acc64", "mix_kahan", "mix_acc32", "f32"))
 def test_adjoint_fp32_pairs_matches_oracle(prec):
     n, S, K = 2048, 40, 20
     x, v, m, y = _problem(n, 70)

@@ -175,3 +175,41 @@ def test_plummer_virial_values():
     assert d["PE"] == pytest.approx(-3 * np.pi / 32, rel=0.04)
     assert d["KE"] == pytest.approx(3 * np.pi / 64, rel=0.04)
     assert 2 * d["KE"] / abs(d["PE"]) == pytest.approx(1.0, abs=0.05)
+
+
+def test_high_precision_kdk_brute_force():
+    # Ten steps of the same scheme carried out at 50 significant digits: the
+    # oracle's FP64 trajectory stays within rounding of it.
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    x, v, m = plummer_sphere(8, 23)
+    eps, dt, S = 2.0 ** -3, 2.0 ** -6, 10
+    n = x.shape[1]
+    mf = [mpmath.mpf(float(q)) for q in m]
+    e2 = mpmath.mpf(eps) ** 2
+
+    def acc(X):
+        out = [[mpmath.mpf(0)] * n for _ in range(3)]
+        for i in range(n):
+            for j in range(n):
+                if j != i:
+                    d = [X[c][j] - X[c][i] for c in range(3)]
+                    w = mf[j] / (d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + e2) ** mpmath.mpf(1.5)
+                    for c in range(3):
+                        out[c][i] += w * d[c]
+        return out
+
+    X = [[mpmath.mpf(float(q)) for q in row] for row in x]
+    V = [[mpmath.mpf(float(q)) for q in row] for row in v]
+    h, dtm = mpmath.mpf(dt) / 2, mpmath.mpf(dt)
+    A = acc(X)
+    for _ in range(S):
+        V = [[V[c][i] + h * A[c][i] for i in range(n)] for c in range(3)]
+        X = [[X[c][i] + dtm * V[c][i] for i in range(n)] for c in range(3)]
+        A = acc(X)
+        V = [[V[c][i] + h * A[c][i] for i in range(n)] for c in range(3)]
+    xo, vo, _ = oracle.kdk(x, v, m, eps, dt, S)
+    xr = np.array([[float(q) for q in row] for row in X])
+    vr = np.array([[float(q) for q in row] for row in V])
+    assert np.max(np.abs(xo - xr)) <= 1e-14 * np.max(np.abs(xr))
+    assert np.max(np.abs(vo - vr)) <= 1e-13 * np.max(np.abs(vr))
