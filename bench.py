@@ -215,7 +215,10 @@ def main():
         e.record(stream)
         return e
 
+    step_events = []
+
     def one_step():
+        s0 = ev()
         x.copy_(X0)
         v.copy_(V0)
         nb.diag(x, v, M, w.eps, prec=prec, out=d0)
@@ -231,6 +234,7 @@ def main():
                         ckpt=ckpt, ckpt_every=K, step_end=R)
         e3 = ev()
         pass_events.append((e0, e1, e2, e3))
+        step_events.append((s0, e3))
 
     for i in range(args.warmup):
         one_step()
@@ -238,6 +242,7 @@ def main():
         print("warmup step %d done" % i, flush=True)
 
     pass_events.clear()
+    step_events.clear()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     _lib.check(L.nbody_profile_begin(), "nbody_profile_begin")
@@ -253,6 +258,7 @@ def main():
     ms_step = ms_total / args.steps
     print("timed %d steps: %.1f ms/step (wall %.1f s)" % (args.steps, ms_step, wall), flush=True)
 
+    step_ms = sorted(a.elapsed_time(b) for a, b in step_events)
     passes_fwd, passes_adj = R + 1, R + 1
     interactions = float(n) * n * (passes_fwd + passes_adj)
     value = interactions / (ms_step * 1e-3) / 1e9
@@ -306,10 +312,20 @@ def main():
         ref = oracle.accel_sampled(xh, mh, w.eps, idx)
         tcpu = time.time() - tc
         rel_err = float(np.linalg.norm(a_gpu[:, idx] - ref) / np.linalg.norm(ref))
+        # the same oracle on one thread, over the first eighth of the sinks
+        k0 = oracle.num_threads()
+        idx1 = idx[: max(1, len(idx) // 8)]
+        oracle.set_num_threads(1)
+        tc = time.time()
+        oracle.accel_sampled(xh, mh, w.eps, idx1)
+        t1 = time.time() - tc
+        oracle.set_num_threads(k0)
         cpu = {"value": len(idx) * float(n) / tcpu / 1e9, "unit": "Ginteractions/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": k0, "kind": "oracle",
                "sample": "%d seeded sinks x all %d sources, FP64 force (%.1f s)"
-                         % (len(idx), n, tcpu)}
+                         % (len(idx), n, tcpu),
+               "one_thread_value": len(idx1) * float(n) / t1 / 1e9,
+               "one_thread_sample": "%d of the same sinks (%.1f s)" % (len(idx1), t1)}
         print("cpu oracle: %.3f Ginteractions/s on %d threads; GPU force rel err %.3g"
               % (cpu["value"], cpu["cores"], rel_err), flush=True)
 
@@ -321,6 +337,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "step_ms_best": step_ms[0],
+        "step_ms_median": step_ms[len(step_ms) // 2],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

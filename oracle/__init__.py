@@ -6,7 +6,7 @@ GPU library itself. It shares no code with it.
 """
 
 from .oracle import (accel, accel_sampled, kdk, diag, vjp, jvp, adjoint, diffusion3d,
-                     num_threads, DIAG_FIELDS)
+                     num_threads, set_num_threads, DIAG_FIELDS)
 
 __all__ = ["accel", "accel_sampled", "kdk", "diag", "vjp", "jvp", "adjoint", "diffusion3d",
-           "num_threads", "DIAG_FIELDS"]
+           "num_threads", "set_num_threads", "DIAG_FIELDS"]

@@ -52,6 +52,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Thread count of later calls (k >= 1); the results do not depend on it. */
+void oracle_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 /*
  * Eq. (1): a_i = G * sum_{j != i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^(3/2)
  * for ni sinks at xi against nj sources at xj with masses mj.

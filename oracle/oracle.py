@@ -43,6 +43,8 @@ def _load():
     lib.oracle_jvp.argtypes = [i64, _D, _D, _D, dbl, dbl, _D]
     lib.oracle_adjoint.argtypes = [i64, i64, _D, _D, dbl, dbl, dbl, _D, _D, _D]
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     for f in ("oracle_accel", "oracle_kdk", "oracle_diag", "oracle_vjp",
               "oracle_jvp", "oracle_adjoint"):
         getattr(lib, f).restype = None
@@ -63,6 +65,11 @@ def _p(a):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads used by later calls (the results do not depend on it)."""
+    _load().oracle_set_num_threads(int(k))
 
 
 def accel(x, m, eps, G=1.0, xj=None, potential=False):

@@ -193,3 +193,17 @@ def test_high_precision_brute_force():
                 acc[c] += mpmath.mpf(m[j]) * d[c] / s ** mpmath.mpf(1.5)
         for c in range(3):
             assert abs(float(acc[c]) - a[c, i]) <= 1e-14 * abs(float(acc[c])) + 1e-300
+
+
+def test_set_num_threads_bitwise():
+    x, _, m = _plummer(300, 19)
+    k0 = oracle.num_threads()
+    a = oracle.accel(x, m, 2.0 ** -6)
+    try:
+        oracle.set_num_threads(1)
+        assert oracle.num_threads() == 1
+        assert np.array_equal(oracle.accel(x, m, 2.0 ** -6), a)
+        oracle.set_num_threads(3)
+        assert np.array_equal(oracle.accel(x, m, 2.0 ** -6), a)
+    finally:
+        oracle.set_num_threads(k0)
