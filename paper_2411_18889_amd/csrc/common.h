@@ -161,6 +161,20 @@ hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi
                         double G, bool self_set, void* acc, void* pot, void* ws,
                         hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0);
 
+// Symmetric (third-law) force pass of one set on itself, NB_MIX_TILEC only:
+// blocks of waves*64*ipl particles; waves == 0 means "not used".
+struct SymShape {
+    int waves;  // wavefronts per workgroup
+    int ipl;    // sinks per lane
+};
+SymShape choose_sym_shape(int prec, int64_t n);
+size_t sym_partials_bytes(const SymShape& s, int64_t n);
+// acc = a(x) (and with kick_v, v <- v + kick_h * acc); ws holds
+// sym_partials_bytes(sh, n) bytes.
+hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
+                            double eps, double G, void* acc, void* ws, hipStream_t stream,
+                            void* kick_v = nullptr, double kick_h = 0.0);
+
 // Fused adjoint pair pass at x with adjoint lam_v: computes a(x), J^T lam_v,
 // G^T lam_v and applies the epilogue
 //   lam_x += c J^T lam_v;  lam_m += c G^T lam_v;

@@ -1,0 +1,286 @@
+// Symmetric pair-force pass of Eq. (1) for one particle set acting on itself
+// (the tile-compensated FP32 policy), on gfx950.
+//
+// Newton's third law: the pair (i, j) exerts m_j d s^-3/2 on i and
+// -m_i d s^-3/2 on j (d = x_j - x_i), so one reciprocal square root and one
+// s^-3/2 serve both bodies: 16 VALU + 1 rsqrt per pair, i.e. 8 VALU + 1/2
+// rsqrt per interaction against 12 + 1 for the one-sided kernel. The cost is
+// that the j side has to be summed across lanes and workgroups; it is done
+// here in a fixed order, without global atomics, so the result is bitwise
+// reproducible:
+//
+//  * the particles are cut into nb blocks of BI = W*64*K; a work item is a
+//    block pair (I, J) with I <= J (nb (nb + 1) / 2 items, one workgroup each);
+//  * item (I, J), I < J: lane l of wave w holds K sinks of block I in
+//    registers; the sources of block J are staged in LDS tiles of TJ, and in
+//    every 64-source group lane l meets source (l + t) mod 64 at step t, so
+//    the 64 lanes touch 64 different sources at every step. The i side is a
+//    running FP32 sum folded into FP64 after each group (as the tile-
+//    compensated policy); the j side of the K pairs of a lane is added with
+//    one LDS float atomic per component into the wave's own accumulator of
+//    that source -- one add per slot per step, in program order, hence a
+//    fixed order. At the end of a tile the W wave accumulators are added in
+//    wave order;
+//  * item (I, I): the block on itself, i side only (each pair from both
+//    ends, the j = i term contributing 0);
+//  * every item writes FP32 partials: its i side for block I into slot J, its
+//    j side for block J into slot I. Each particle of block P so receives
+//    exactly one partial in each slot k = 0 .. nb-1 (k < P: j side of item
+//    (k, P); k = P: item (P, P); k > P: i side of item (P, k)), and a second
+//    kernel adds the nb slots in slot order in FP64, then applies G and the
+//    optional closing half-kick.
+#include "common.h"
+
+namespace nb {
+
+namespace {
+
+constexpr int TJ = 256;  // sources per LDS tile
+
+struct SymArgs {
+    const double *x, *y, *z;
+    const float* m;
+    int n, nb;
+    float eps2;
+    float* part;  // [nb][3][n]
+};
+
+struct SymFinishArgs {
+    const float* part;
+    int n, nb;
+    double G;
+    double *ax, *ay, *az;
+    double *vx, *vy, *vz;  // or nullptr
+    double h;
+};
+
+__device__ __forceinline__ void lds_add(float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One tile of sources (rec[0 .. TJ)) against the K sinks of this lane.
+template <int K, bool JSIDE>
+__device__ __forceinline__ void sym_tile(const float4* rec, float* jx, float* jy, float* jz,
+                                         const float* xi, const float* yi, const float* zi,
+                                         const float* mi, SumTile (*s)[3], float eps2, int lane) {
+    for (int g = 0; g < TJ; g += 64) {
+#pragma unroll 4
+        for (int t = 0; t < 64; ++t) {
+            const int jj = g + ((lane + t) & 63);
+            const float4 q = rec[jj];
+            float cx = 0.f, cy = 0.f, cz = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float dx = q.x - xi[k];
+                const float dy = q.y - yi[k];
+                const float dz = q.z - zi[k];
+                const float ss = fmat(dz, dz, fmat(dy, dy, fmat(dx, dx, eps2)));
+                const float r = rsqrt_pair(ss);
+                const float r3 = r * (r * r);
+                const float wj = r3 * q.w;
+                s[k][0].add_fma(dx, wj);
+                s[k][1].add_fma(dy, wj);
+                s[k][2].add_fma(dz, wj);
+                if (JSIDE) {
+                    const float wi = r3 * mi[k];
+                    cx = fmat(dx, wi, cx);
+                    cy = fmat(dy, wi, cy);
+                    cz = fmat(dz, wi, cz);
+                }
+            }
+            if (JSIDE) {
+                lds_add(jx + jj, cx);
+                lds_add(jy + jj, cy);
+                lds_add(jz + jj, cz);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            s[k][0].tile_end();
+            s[k][1].tile_end();
+            s[k][2].tile_end();
+        }
+    }
+}
+
+template <int W, int K>
+__global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
+    constexpr int NT = W * 64;
+    constexpr int BI = NT * K;
+    static_assert(BI % TJ == 0, "a block must hold whole tiles");
+    __shared__ float4 rec[TJ];
+    __shared__ float jacc[W][3][TJ];
+
+    // item -> (I, J), I <= J, items ordered by J then I
+    const int64_t item = blockIdx.x;
+    int J = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) * 0.5);
+    while ((int64_t)J * (J + 1) / 2 > item) --J;
+    while ((int64_t)(J + 1) * (J + 2) / 2 <= item) ++J;
+    const int I = (int)(item - (int64_t)J * (J + 1) / 2);
+    const bool jside = I != J;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int ibase = I * BI + w * 64 * K + lane;
+    float xi[K], yi[K], zi[K], mi[K];
+    SumTile s[K][3];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ibase + k * 64;
+        const bool ok = i < a.n;
+        xi[k] = ok ? float(a.x[i]) : 0.f;
+        yi[k] = ok ? float(a.y[i]) : 0.f;
+        zi[k] = ok ? float(a.z[i]) : 0.f;
+        mi[k] = ok ? a.m[i] : 0.f;  // a padding sink adds exactly 0 to the j side
+        s[k][0].init();
+        s[k][1].init();
+        s[k][2].init();
+    }
+    float* flat = &jacc[0][0][0];
+    for (int q = tid; q < W * 3 * TJ; q += NT) flat[q] = 0.f;
+
+    const int jb = J * BI;
+    const int je = min(a.n, jb + BI);
+    for (int jt = jb; jt < je; jt += TJ) {
+        for (int q = tid; q < TJ; q += NT) {
+            const int j = jt + q;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);  // zero-mass padding
+            if (j < je) p = make_float4(float(a.x[j]), float(a.y[j]), float(a.z[j]), a.m[j]);
+            rec[q] = p;
+        }
+        __syncthreads();
+        if (jside)
+            sym_tile<K, true>(rec, jacc[w][0], jacc[w][1], jacc[w][2], xi, yi, zi, mi, s, a.eps2,
+                              lane);
+        else
+            sym_tile<K, false>(rec, nullptr, nullptr, nullptr, xi, yi, zi, mi, s, a.eps2, lane);
+        __syncthreads();
+        if (jside) {
+            // j side of this tile: the wave accumulators in wave order, then
+            // cleared for the next tile (the barrier before its pair loop
+            // orders the clearing before the next adds)
+            for (int q = tid; q < 3 * TJ; q += NT) {
+                const int c = q / TJ, jj = q - c * TJ;
+                float sum = 0.f;
+#pragma unroll
+                for (int v = 0; v < W; ++v) {
+                    sum += jacc[v][c][jj];
+                    jacc[v][c][jj] = 0.f;
+                }
+                const int j = jt + jj;
+                if (j < je) a.part[((size_t)I * 3 + c) * a.n + j] = -sum;
+            }
+        }
+        // rec is rewritten only after every wave has passed the barrier above
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ibase + k * 64;
+        if (i >= a.n) continue;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.part[((size_t)J * 3 + c) * a.n + i] = float(s[k][c].total());
+    }
+}
+
+// Adds the nb partials of every particle in slot order (FP64), then stores
+// a = G * sum and applies the optional half-kick v <- v + h a, with a as stored.
+__global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int k = 0; k < a.nb; ++k) {
+        const float* p = a.part + (size_t)k * 3 * a.n;
+        sx += double(p[i]);
+        sy += double(p[(size_t)a.n + i]);
+        sz += double(p[(size_t)2 * a.n + i]);
+    }
+    const double ax = a.G * sx, ay = a.G * sy, az = a.G * sz;
+    a.ax[i] = ax;
+    a.ay[i] = ay;
+    a.az[i] = az;
+    if (a.vx) {
+        a.vx[i] = a.vx[i] + a.h * ax;
+        a.vy[i] = a.vy[i] + a.h * ay;
+        a.vz[i] = a.vz[i] + a.h * az;
+    }
+}
+
+template <int W, int K>
+hipError_t launch_sym(const SymArgs& a, hipStream_t stream) {
+    const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
+    hipLaunchKernelGGL((force_sym_kernel<W, K>), dim3((unsigned)items), dim3(W * 64), 0, stream, a);
+    return hipGetLastError();
+}
+
+constexpr size_t kSymWorkspaceCap = size_t(16) << 30;
+
+}  // namespace
+
+SymShape choose_sym_shape(int prec, int64_t n) {
+    // Blocks of BI = W*64*K particles; at least 64 blocks (2080 equal work
+    // items, ~8 per CU) so that the triangle of block pairs balances the
+    // 256 CUs; two or more sinks per lane so that the three LDS adds of the
+    // j side are shared by several pairs.
+    SymShape s{0, 0};
+    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return s;
+    const int64_t bi = n / 64;
+    if (bi >= 4096) s = SymShape{16, 4};
+    else if (bi >= 2048) s = SymShape{8, 4};
+    else if (bi >= 1024) s = SymShape{8, 2};
+    else if (bi >= 512) s = SymShape{4, 2};
+    else s = SymShape{2, 2};
+    if (sym_partials_bytes(s, n) > kSymWorkspaceCap) return SymShape{0, 0};
+    return s;
+}
+
+size_t sym_partials_bytes(const SymShape& s, int64_t n) {
+    if (s.waves == 0) return 0;
+    const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
+    const int64_t nb = (n + bi - 1) / bi;
+    return (size_t)nb * 3 * (size_t)n * sizeof(float);
+}
+
+hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
+                            double eps, double G, void* acc, void* ws, hipStream_t stream,
+                            void* kick_v, double kick_h) {
+    const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
+    if (bi == 0) return hipErrorInvalidValue;
+    SymArgs a{};
+    const double* p = static_cast<const double*>(x);
+    a.x = p;
+    a.y = p + n;
+    a.z = p + 2 * n;
+    a.m = static_cast<const float*>(m);
+    a.n = (int)n;
+    a.nb = (int)((n + bi - 1) / bi);
+    a.eps2 = float(eps) * float(eps);
+    a.part = static_cast<float*>(ws);
+    hipError_t e = hipErrorInvalidValue;
+#define NB_SYM_CASE(WV, KV) \
+    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<WV, KV>(a, stream);
+    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(8, 2) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+#undef NB_SYM_CASE
+    if (e != hipSuccess) return e;
+    SymFinishArgs f{};
+    f.part = a.part;
+    f.n = a.n;
+    f.nb = a.nb;
+    f.G = G;
+    double* po = static_cast<double*>(acc);
+    f.ax = po;
+    f.ay = po + n;
+    f.az = po + 2 * n;
+    if (kick_v) {
+        double* pv = static_cast<double*>(kick_v);
+        f.vx = pv;
+        f.vy = pv + n;
+        f.vz = pv + 2 * n;
+        f.h = kick_h;
+    }
+    hipLaunchKernelGGL(force_sym_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       stream, f);
+    return hipGetLastError();
+}
+
+}  // namespace nb

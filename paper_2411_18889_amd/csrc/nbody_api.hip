@@ -220,6 +220,9 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
                 overlaps(pot, (size_t)ni * ps, xi, 3 * (size_t)ni * ps) ||
                 overlaps(pot, (size_t)ni * ps, xj, 3 * (size_t)nj * ps)))
         return NB_EINVAL;
+    // one set on itself, no potential, library shape: the symmetric pass
+    // where the policy has one
+    const SymShape sym = (self_set && !pot && !launch) ? choose_sym_shape(prec, ni) : SymShape{0, 0};
     Shape sh = choose_force_shape(prec, ni, nj);
     if (launch) {
         if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
@@ -227,11 +230,12 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
         if (launch->split) sh.split = launch->split;
         if (!shape_supported(sh)) return NB_EUNSUPPORTED;
     }
-    int st = check_ws(ws, ws_bytes, accel_ws(sh, ni));
+    int st = check_ws(ws, ws_bytes, sym.waves ? sym_partials_bytes(sym, ni) : accel_ws(sh, ni));
     if (st != NB_OK) return st;
     if ((st = check_device()) != NB_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return hip_status(timed(NB_PROF_FORCE, s, [&] {
+        if (sym.waves) return launch_force_sym(sym, ni, xi, mj, eps, G, acc, ws, s);
         return launch_force(prec, sh, ni, xi, nj, xj, mj, eps, G, self_set, acc, pot, ws, s);
     }));
 }
@@ -273,7 +277,8 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
             return NB_EINVAL;
     }
     const Shape sh = choose_force_shape(prec, n, n);
-    int st = check_ws(ws, ws_bytes, accel_ws(sh, n));
+    const SymShape sym = choose_sym_shape(prec, n);
+    int st = check_ws(ws, ws_bytes, sym.waves ? sym_partials_bytes(sym, n) : accel_ws(sh, n));
     if (st != NB_OK) return st;
     if ((st = check_device()) != NB_OK) return st;
 
@@ -285,6 +290,8 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
         // v <- v + h a in the same launch (the pair pass never reads v)
         auto force = [&](bool kick) {
             return timed(NB_PROF_FORCE, q, [&] {
+                if (sym.waves)
+                    return launch_force_sym(sym, n, x, m, eps, G, acc, ws, q, kick ? v : nullptr, h);
                 return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, q,
                                     kick ? v : nullptr, h);
             });
@@ -457,9 +464,15 @@ int diffusion3d_step(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, d
 size_t nbody_workspace_size(int op, int64_t n, int prec) {
     if (!valid_prec(prec) || n < 1 || n > kMaxN) return 0;
     switch (op) {
-    case NB_OP_ACCEL:
-    case NB_OP_STEP:
-        return accel_ws(choose_force_shape(prec, n, n), n);
+    case NB_OP_ACCEL: {  // either pass may run
+        const size_t a = accel_ws(choose_force_shape(prec, n, n), n);
+        const size_t b = sym_partials_bytes(choose_sym_shape(prec, n), n);
+        return a > b ? a : b;
+    }
+    case NB_OP_STEP: {
+        const SymShape sym = choose_sym_shape(prec, n);
+        return sym.waves ? sym_partials_bytes(sym, n) : accel_ws(choose_force_shape(prec, n, n), n);
+    }
     case NB_OP_ADJOINT: {
         const Shape sh = choose_adjoint_shape(prec, n);
         return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;

@@ -55,6 +55,12 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 4096, TILEC) > 0       # split source ranges: partials
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) > 0
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
+    # a set acting on itself with the tile-compensated policy from 16384 on:
+    # the symmetric pass, one FP32 partial per particle, component and block
+    # (blocks of n/64 particles up to 4096)
+    assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
+    assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 256 * 3 * (1 << 20) * 4
+    assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
 
 
 def _accel(L, ni=64, xi=A, nj=64, xj=B, mj=C, eps=0.1, G=1.0, prec=F64, acc=D, pot=None,
