@@ -1,0 +1,307 @@
+// Symmetric (third-law) form of the fused adjoint pair pass for the
+// tile-compensated FP32 policy, on gfx950.
+//
+// With d = x_j - x_i, s = |d|^2 + eps^2, T(d) = s^-3/2 I - 3 s^-5/2 d d^T and
+// u = m_i lam_j - m_j lam_i, the pair (i, j) adds
+//   to i:  m_j s^-3/2 d,   T(d) u,    s^-3/2 (lam_j . d)
+//   to j: -m_i s^-3/2 d,  -T(d) u,   -s^-3/2 (lam_i . d)
+// (T is even in d and u is odd under the swap), so one reciprocal square
+// root, one T(d) u and one s^-3/2 serve both ends: 44 VALU + 1 rsqrt per
+// pair, i.e. 22 VALU + 1/2 rsqrt per interaction against 34 + 1 one-sided.
+// The blocking, the work items (block pairs I <= J), the per-wave LDS
+// accumulators of the source side and the fixed-order FP32 partials are
+// those of the symmetric force pass, with seven quantities instead of three:
+// a (3), J^T lam (3) and the mass-adjoint sum (1). The finishing kernel adds
+// the partials in slot order in FP64 and applies the adjoint epilogue of the
+// reverse walk.
+#include "common.h"
+
+namespace nb {
+
+namespace {
+
+constexpr int TJ = 128;  // sources per LDS tile
+constexpr int NQ = 7;
+
+struct ASymArgs {
+    const double *x, *y, *z;
+    const float* m;
+    const double *lx, *ly, *lz;  // lam_v
+    int n, nb;
+    float eps2;
+    float* part;  // [nb][NQ][n]
+};
+
+struct ASymFinishArgs {
+    const float* part;
+    int n, nb;
+    double G, c, h;
+    int update_state;
+    double *ax, *ay, *az;
+    double *vx, *vy, *vz;
+    double *gx, *gy, *gz;
+    double* gm;
+};
+
+__device__ __forceinline__ void lds_add(float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int K, bool JSIDE>
+__device__ __forceinline__ void asym_tile(const float4* rp, const float4* rl, float* jq,
+                                          const float* xi, const float* yi, const float* zi,
+                                          const float* mi, const float* lxi, const float* lyi,
+                                          const float* lzi, SumTile (*s)[NQ], float eps2,
+                                          int lane) {
+    for (int g = 0; g < TJ; g += 64) {
+#pragma unroll 2
+        for (int t = 0; t < 64; ++t) {
+            const int jj = g + ((lane + t) & 63);
+            const float4 q = rp[jj];
+            const float4 lj = rl[jj];
+            float c[NQ];
+#pragma unroll
+            for (int p = 0; p < NQ; ++p) c[p] = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const float dx = q.x - xi[k];
+                const float dy = q.y - yi[k];
+                const float dz = q.z - zi[k];
+                const float ss = fmat(dz, dz, fmat(dy, dy, fmat(dx, dx, eps2)));
+                const float r = rsqrt_pair(ss);
+                const float r2 = r * r;
+                const float r3 = r2 * r;
+                const float wj = r3 * q.w;
+                s[k][0].add_fma(dx, wj);
+                s[k][1].add_fma(dy, wj);
+                s[k][2].add_fma(dz, wj);
+                const float ux = fmat(mi[k], lj.x, -(q.w * lxi[k]));
+                const float uy = fmat(mi[k], lj.y, -(q.w * lyi[k]));
+                const float uz = fmat(mi[k], lj.z, -(q.w * lzi[k]));
+                const float du = fmat(dz, uz, fmat(dy, uy, dx * ux));
+                const float e = (-3.f * r2) * du;
+                const float tx = fmat(e, dx, ux);
+                const float ty = fmat(e, dy, uy);
+                const float tz = fmat(e, dz, uz);
+                s[k][3].add_fma(r3, tx);
+                s[k][4].add_fma(r3, ty);
+                s[k][5].add_fma(r3, tz);
+                const float dl = fmat(dz, lj.z, fmat(dy, lj.y, dx * lj.x));
+                s[k][6].add_fma(r3, dl);
+                if (JSIDE) {
+                    const float wi = r3 * mi[k];
+                    c[0] = fmat(dx, wi, c[0]);
+                    c[1] = fmat(dy, wi, c[1]);
+                    c[2] = fmat(dz, wi, c[2]);
+                    c[3] = fmat(r3, tx, c[3]);
+                    c[4] = fmat(r3, ty, c[4]);
+                    c[5] = fmat(r3, tz, c[5]);
+                    const float dli = fmat(dz, lzi[k], fmat(dy, lyi[k], dx * lxi[k]));
+                    c[6] = fmat(r3, dli, c[6]);
+                }
+            }
+            if (JSIDE) {
+#pragma unroll
+                for (int p = 0; p < NQ; ++p) lds_add(jq + p * TJ + jj, c[p]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int p = 0; p < NQ; ++p) s[k][p].tile_end();
+    }
+}
+
+template <int W, int K>
+__global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
+    constexpr int NT = W * 64;
+    constexpr int BI = NT * K;
+    static_assert(BI % TJ == 0, "a block must hold whole tiles");
+    __shared__ float4 rp[TJ];
+    __shared__ float4 rl[TJ];
+    __shared__ float jacc[W][NQ][TJ];
+
+    const int64_t item = blockIdx.x;
+    int J = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) * 0.5);
+    while ((int64_t)J * (J + 1) / 2 > item) --J;
+    while ((int64_t)(J + 1) * (J + 2) / 2 <= item) ++J;
+    const int I = (int)(item - (int64_t)J * (J + 1) / 2);
+    const bool jside = I != J;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int ibase = I * BI + w * 64 * K + lane;
+    float xi[K], yi[K], zi[K], mi[K], lxi[K], lyi[K], lzi[K];
+    SumTile s[K][NQ];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ibase + k * 64;
+        const bool ok = i < a.n;
+        xi[k] = ok ? float(a.x[i]) : 0.f;
+        yi[k] = ok ? float(a.y[i]) : 0.f;
+        zi[k] = ok ? float(a.z[i]) : 0.f;
+        mi[k] = ok ? a.m[i] : 0.f;  // a padding sink adds exactly 0 to the j side
+        lxi[k] = ok ? float(a.lx[i]) : 0.f;
+        lyi[k] = ok ? float(a.ly[i]) : 0.f;
+        lzi[k] = ok ? float(a.lz[i]) : 0.f;
+#pragma unroll
+        for (int p = 0; p < NQ; ++p) s[k][p].init();
+    }
+    float* flat = &jacc[0][0][0];
+    for (int q = tid; q < W * NQ * TJ; q += NT) flat[q] = 0.f;
+
+    const int jb = J * BI;
+    const int je = min(a.n, jb + BI);
+    for (int jt = jb; jt < je; jt += TJ) {
+        for (int q = tid; q < TJ; q += NT) {
+            const int j = jt + q;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);  // zero mass and adjoint: adds 0
+            float4 l = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < je) {
+                p = make_float4(float(a.x[j]), float(a.y[j]), float(a.z[j]), a.m[j]);
+                l = make_float4(float(a.lx[j]), float(a.ly[j]), float(a.lz[j]), 0.f);
+            }
+            rp[q] = p;
+            rl[q] = l;
+        }
+        __syncthreads();
+        if (jside)
+            asym_tile<K, true>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2,
+                               lane);
+        else
+            asym_tile<K, false>(rp, rl, nullptr, xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2, lane);
+        __syncthreads();
+        if (jside) {
+            for (int q = tid; q < NQ * TJ; q += NT) {
+                const int p = q / TJ, jj = q - p * TJ;
+                float sum = 0.f;
+#pragma unroll
+                for (int v = 0; v < W; ++v) {
+                    sum += jacc[v][p][jj];
+                    jacc[v][p][jj] = 0.f;
+                }
+                const int j = jt + jj;
+                if (j < je) a.part[((size_t)I * NQ + p) * a.n + j] = -sum;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = ibase + k * 64;
+        if (i >= a.n) continue;
+#pragma unroll
+        for (int p = 0; p < NQ; ++p)
+            a.part[((size_t)J * NQ + p) * a.n + i] = float(s[k][p].total());
+    }
+}
+
+// Slot-ordered FP64 sum of the partials, then the reverse-walk epilogue:
+//   lam_x += c G J^T lam;  lam_m += c (-G) G^T-sum;
+//   if update_state: acc = G a_sum; v <- v - h acc.
+__global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs a) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    double q[NQ] = {0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < a.nb; ++k) {
+        const float* p = a.part + (size_t)k * NQ * a.n + i;
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q[c] += double(p[(size_t)c * a.n]);
+    }
+    const double G = a.G, c = a.c;
+    a.gx[i] = a.gx[i] + c * (G * q[3]);
+    a.gy[i] = a.gy[i] + c * (G * q[4]);
+    a.gz[i] = a.gz[i] + c * (G * q[5]);
+    a.gm[i] = a.gm[i] + c * (-G * q[6]);
+    if (a.update_state) {
+        const double ax = G * q[0], ay = G * q[1], az = G * q[2];
+        a.ax[i] = ax;
+        a.ay[i] = ay;
+        a.az[i] = az;
+        a.vx[i] = a.vx[i] - a.h * ax;
+        a.vy[i] = a.vy[i] - a.h * ay;
+        a.vz[i] = a.vz[i] - a.h * az;
+    }
+}
+
+template <int W, int K>
+hipError_t launch_asym(const ASymArgs& a, hipStream_t stream) {
+    const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
+    hipLaunchKernelGGL((adjoint_sym_kernel<W, K>), dim3((unsigned)items), dim3(W * 64), 0, stream,
+                       a);
+    return hipGetLastError();
+}
+
+constexpr size_t kAdjSymWorkspaceCap = size_t(16) << 30;
+
+}  // namespace
+
+SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
+    // As the force pass: >= 64 blocks, two or more sinks per lane; blocks of
+    // at most 2048 (8 waves x 4 sinks: the 7 running sums per sink keep
+    // larger blocks from fitting the register file).
+    SymShape s{0, 0};
+    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return s;
+    const int64_t bi = n / 64;
+    if (bi >= 2048) s = SymShape{8, 4};
+    else if (bi >= 1024) s = SymShape{8, 2};
+    else if (bi >= 512) s = SymShape{4, 2};
+    else s = SymShape{2, 2};
+    if (adjoint_sym_partials_bytes(s, n) > kAdjSymWorkspaceCap) return SymShape{0, 0};
+    return s;
+}
+
+size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n) {
+    if (s.waves == 0) return 0;
+    const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
+    const int64_t nb = (n + bi - 1) / bi;
+    return (size_t)nb * NQ * (size_t)n * sizeof(float);
+}
+
+hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
+                              const void* lam_v, double eps, double G, double c,
+                              bool update_state, double h, void* acc, void* v, void* lam_x,
+                              double* lam_m, void* ws, hipStream_t stream) {
+    const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
+    if (bi == 0) return hipErrorInvalidValue;
+    ASymArgs a{};
+    const double* px = static_cast<const double*>(x);
+    const double* pl = static_cast<const double*>(lam_v);
+    a.x = px;
+    a.y = px + n;
+    a.z = px + 2 * n;
+    a.m = static_cast<const float*>(m);
+    a.lx = pl;
+    a.ly = pl + n;
+    a.lz = pl + 2 * n;
+    a.n = (int)n;
+    a.nb = (int)((n + bi - 1) / bi);
+    a.eps2 = float(eps) * float(eps);
+    a.part = static_cast<float*>(ws);
+    hipError_t e = hipErrorInvalidValue;
+#define NB_ASYM_CASE(WV, KV) \
+    if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, stream);
+    NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(8, 4)
+#undef NB_ASYM_CASE
+    if (e != hipSuccess) return e;
+    ASymFinishArgs f{};
+    f.part = a.part;
+    f.n = a.n;
+    f.nb = a.nb;
+    f.G = G;
+    f.c = c;
+    f.h = h;
+    f.update_state = update_state ? 1 : 0;
+    double* pa = static_cast<double*>(acc);
+    double* pv = static_cast<double*>(v);
+    double* pg = static_cast<double*>(lam_x);
+    f.ax = pa; f.ay = pa + n; f.az = pa + 2 * n;
+    f.vx = pv; f.vy = pv + n; f.vz = pv + 2 * n;
+    f.gx = pg; f.gy = pg + n; f.gz = pg + 2 * n;
+    f.gm = lam_m;
+    hipLaunchKernelGGL(adjoint_sym_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       stream, f);
+    return hipGetLastError();
+}
+
+}  // namespace nb

@@ -184,6 +184,15 @@ hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x
                           double c, bool update_state, double h, void* acc, void* v,
                           void* lam_x, double* lam_m, void* ws, hipStream_t stream);
 
+// Symmetric form of the fused adjoint pass (NB_MIX_TILEC only), same
+// contract as launch_adjoint; ws holds adjoint_sym_partials_bytes(sh, n).
+SymShape choose_adjoint_sym_shape(int prec, int64_t n);
+size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n);
+hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
+                              const void* lam_v, double eps, double G, double c,
+                              bool update_state, double h, void* acc, void* v, void* lam_x,
+                              double* lam_m, void* ws, hipStream_t stream);
+
 // O(N) leapfrog kernels over the 3n components of a pos array.
 hipError_t launch_kick_drift(int prec, int64_t n, void* x, void* v, const void* acc,
                              double h, double dt, hipStream_t stream);

@@ -387,7 +387,9 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
             if (overlaps(ckpt, cb, bufs[p], sizes[p])) return NB_EINVAL;
     }
     const Shape sh = choose_adjoint_shape(prec, n);
-    const size_t need = sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
+    const SymShape sym = choose_adjoint_sym_shape(prec, n);
+    const size_t need = sym.waves ? adjoint_sym_partials_bytes(sym, n)
+                                  : (sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0);
     int st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
     if ((st = check_device()) != NB_OK) return st;
@@ -398,6 +400,9 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
     hipError_t e = hipSuccess;
     auto fused = [&](double c, bool update_state) {
         return timed(NB_PROF_ADJOINT, s, [&] {
+            if (sym.waves)
+                return launch_adjoint_sym(sym, n, x, m, lam_v, eps, G, c, update_state, h, acc, v,
+                                          lam_x, lm, ws, s);
             return launch_adjoint(prec, sh, n, x, m, lam_v, eps, G, c, update_state, h, acc, v, lam_x,
                                   lm, ws, s);
         });
@@ -474,6 +479,8 @@ size_t nbody_workspace_size(int op, int64_t n, int prec) {
         return sym.waves ? sym_partials_bytes(sym, n) : accel_ws(choose_force_shape(prec, n, n), n);
     }
     case NB_OP_ADJOINT: {
+        const SymShape sym = choose_adjoint_sym_shape(prec, n);
+        if (sym.waves) return adjoint_sym_partials_bytes(sym, n);
         const Shape sh = choose_adjoint_shape(prec, n);
         return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
     }

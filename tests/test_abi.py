@@ -61,6 +61,10 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
     assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 256 * 3 * (1 << 20) * 4
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
+    # and the symmetric adjoint pass: seven FP32 partials per particle and
+    # block (blocks of n/64 particles up to 2048)
+    assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
+    assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 512 * 7 * (1 << 20) * 4
 
 
 def _accel(L, ni=64, xi=A, nj=64, xj=B, mj=C, eps=0.1, G=1.0, prec=F64, acc=D, pot=None,

@@ -80,6 +80,24 @@ def test_adjoint_fp32_pairs_matches_oracle(prec):
     assert max(errs) <= 1e-4
 
 
+@pytest.mark.parametrize("n", (16384, 16384 + 300, 33000))
+def test_adjoint_symmetric_pass_matches_oracle(n):
+    """From 16384 particles on, the tile-compensated policy walks back with
+    the symmetric (third-law) adjoint pass: blocks of n/64, ragged last
+    blocks. Checked against the oracle's gradient and against the one-sided
+    kernel (FP64-summed policy) on every particle."""
+    S, K = 3, 2
+    x, v, m, y = _problem(n, 90 + n % 7)
+    eps, dt = 2.0 ** -7, 2.0 ** -8
+    gx, gv, gm, (x0, v0, m0) = _gpu_grads(x, v, m, y, eps, dt, S, K, "mix_tilec")
+    ox, ov, om = _oracle_grads(x0, v0, m0, y, eps, dt, S)
+    errs = (rel(gx, ox), rel(gv, ov), rel(gm, om))
+    print("n=%d symmetric adjoint gradient rel err x0 %.3g v0 %.3g m %.3g" % ((n,) + errs))
+    assert max(errs) <= 1e-4
+    cx, cv, cm, _ = _gpu_grads(x, v, m, y, eps, dt, S, K, "mix_acc64")
+    assert rel(gx, cx) <= 1e-5 and rel(gv, cv) <= 1e-5 and rel(gm, cm) <= 1e-4
+
+
 def test_checkpoint_interval_invariance():
     n, S = 512, 12
     x, v, m, y = _problem(n, 80)
@@ -112,8 +130,9 @@ def test_split_calls_equal_one_call():
     assert float((xd - torch.tensor(x, device=DEV)).abs().max()) <= 1e-12
 
 
-def test_position_adjoint_sum_invariant_on_gpu():
-    n, S = 4096, 8
+@pytest.mark.parametrize("n", (4096, 20000))
+def test_position_adjoint_sum_invariant_on_gpu(n):
+    S = 8
     x, v, m, _ = _problem(n, 82)
     eps, dt = 2.0 ** -7, 2.0 ** -8
     xd, vd, md = to_dev(x, v, m, "mix_tilec")
