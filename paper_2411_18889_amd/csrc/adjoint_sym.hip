@@ -8,9 +8,9 @@
 // (T is even in d and u is odd under the swap), so one reciprocal square
 // root, one T(d) u and one s^-3/2 serve both ends: 44 VALU + 1 rsqrt per
 // pair, i.e. 22 VALU + 1/2 rsqrt per interaction against 34 + 1 one-sided.
-// The blocking, the work items (block pairs I <= J), the per-wave LDS
-// accumulators of the source side and the fixed-order FP32 partials are
-// those of the symmetric force pass, with seven quantities instead of three:
+// The blocking, the work items (block pairs I <= J), the source-side sums
+// carried through the lanes and the fixed-order FP32 partials are those of
+// the symmetric force pass, with seven quantities instead of three:
 // a (3), J^T lam (3) and the mass-adjoint sum (1). The finishing kernel adds
 // the partials in slot order in FP64 and applies the adjoint epilogue of the
 // reverse walk.
@@ -43,25 +43,30 @@ struct ASymFinishArgs {
     double* gm;
 };
 
-__device__ __forceinline__ void lds_add(float* p, float v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Lane l receives the value of lane (l + 1) mod 64 (DPP wave_rol:1).
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
 }
 
 template <int K, bool JSIDE>
-__device__ __forceinline__ void asym_tile(const float4* rp, const float4* rl, float* jq,
+__device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 (*rl)[128], float* jq,
                                           const float* xi, const float* yi, const float* zi,
                                           const float* mi, const float* lxi, const float* lyi,
                                           const float* lzi, SumTile (*s)[NQ], float eps2,
                                           int lane) {
-    for (int g = 0; g < TJ; g += 64) {
+    // groups of 64 sources stored twice in a row: lane l reads source
+    // (l + t) mod 64 at rp[g][l + t] (see the force pass)
+    for (int g = 0; g < TJ / 64; ++g) {
+        const float4* rowp = rp[g] + lane;
+        const float4* rowl = rl[g] + lane;
+        // j-side sums of the group's sources, carried one lane down per step
+        float c[NQ];
+#pragma unroll
+        for (int p = 0; p < NQ; ++p) c[p] = 0.f;
 #pragma unroll 2
         for (int t = 0; t < 64; ++t) {
-            const int jj = g + ((lane + t) & 63);
-            const float4 q = rp[jj];
-            const float4 lj = rl[jj];
-            float c[NQ];
-#pragma unroll
-            for (int p = 0; p < NQ; ++p) c[p] = 0.f;
+            const float4 q = rowp[t];
+            const float4 lj = rowl[t];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float dx = q.x - xi[k];
@@ -102,8 +107,12 @@ __device__ __forceinline__ void asym_tile(const float4* rp, const float4* rl, fl
             }
             if (JSIDE) {
 #pragma unroll
-                for (int p = 0; p < NQ; ++p) lds_add(jq + p * TJ + jj, c[p]);
+                for (int p = 0; p < NQ; ++p) c[p] = from_next_lane(c[p]);
             }
+        }
+        if (JSIDE) {  // back in the lane that owns the source
+#pragma unroll
+            for (int p = 0; p < NQ; ++p) jq[p * TJ + g * 64 + lane] = c[p];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k)
@@ -117,8 +126,8 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
     constexpr int NT = W * 64;
     constexpr int BI = NT * K;
     static_assert(BI % TJ == 0, "a block must hold whole tiles");
-    __shared__ float4 rp[TJ];
-    __shared__ float4 rl[TJ];
+    __shared__ float4 rp[TJ / 64][128];
+    __shared__ float4 rl[TJ / 64][128];
     __shared__ float jacc[W][NQ][TJ];
 
     const int64_t item = blockIdx.x;
@@ -148,8 +157,6 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
 #pragma unroll
         for (int p = 0; p < NQ; ++p) s[k][p].init();
     }
-    float* flat = &jacc[0][0][0];
-    for (int q = tid; q < W * NQ * TJ; q += NT) flat[q] = 0.f;
 
     const int jb = J * BI;
     const int je = min(a.n, jb + BI);
@@ -162,8 +169,10 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
                 p = make_float4(float(a.x[j]), float(a.y[j]), float(a.z[j]), a.m[j]);
                 l = make_float4(float(a.lx[j]), float(a.ly[j]), float(a.lz[j]), 0.f);
             }
-            rp[q] = p;
-            rl[q] = l;
+            rp[q >> 6][q & 63] = p;
+            rp[q >> 6][(q & 63) + 64] = p;
+            rl[q >> 6][q & 63] = l;
+            rl[q >> 6][(q & 63) + 64] = l;
         }
         __syncthreads();
         if (jside)
@@ -177,10 +186,7 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
                 const int p = q / TJ, jj = q - p * TJ;
                 float sum = 0.f;
 #pragma unroll
-                for (int v = 0; v < W; ++v) {
-                    sum += jacc[v][p][jj];
-                    jacc[v][p][jj] = 0.f;
-                }
+                for (int v = 0; v < W; ++v) sum += jacc[v][p][jj];
                 const int j = jt + jj;
                 if (j < je) a.part[((size_t)I * NQ + p) * a.n + j] = -sum;
             }
@@ -237,18 +243,20 @@ constexpr size_t kAdjSymWorkspaceCap = size_t(16) << 30;
 }  // namespace
 
 SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
-    // As the force pass: >= 64 blocks, two or more sinks per lane; blocks of
-    // at most 2048 (8 waves x 4 sinks: the 7 running sums per sink keep
-    // larger blocks from fitting the register file).
-    SymShape s{0, 0};
-    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return s;
-    const int64_t bi = n / 64;
-    if (bi >= 2048) s = SymShape{8, 4};
-    else if (bi >= 1024) s = SymShape{8, 2};
-    else if (bi >= 512) s = SymShape{4, 2};
-    else s = SymShape{2, 2};
-    if (adjoint_sym_partials_bytes(s, n) > kAdjSymWorkspaceCap) return SymShape{0, 0};
-    return s;
+    // Measured on MI355X: two sinks per lane (the seven running sums per
+    // sink already take ~126 VGPRs; four take ~254 and halve the waves per
+    // SIMD) and blocks of 512 at N = 2^18; blocks are kept to at most n/64
+    // and grown, with more waves per workgroup, while the FP32 partials
+    // (nb * 7 * n floats) would pass the workspace cap (blocks of 2048 at
+    // 2^20); past the largest block the one-sided kernel is used.
+    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    static const SymShape cands[] = {{2, 2}, {4, 2}, {8, 2}, {16, 2}};  // 256 .. 2048
+    constexpr int NC = 4;
+    auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
+    int k = 0;
+    while (k + 1 < NC && bi(cands[k + 1]) <= 512 && bi(cands[k + 1]) <= n / 64) ++k;
+    while (k < NC && adjoint_sym_partials_bytes(cands[k], n) > kAdjSymWorkspaceCap) ++k;
+    return k < NC ? cands[k] : SymShape{0, 0};
 }
 
 size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n) {
@@ -281,7 +289,7 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     hipError_t e = hipErrorInvalidValue;
 #define NB_ASYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, stream);
-    NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(8, 4)
+    NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(8, 4) NB_ASYM_CASE(16, 2)
 #undef NB_ASYM_CASE
     if (e != hipSuccess) return e;
     ASymFinishArgs f{};

@@ -16,11 +16,11 @@
 //    every 64-source group lane l meets source (l + t) mod 64 at step t, so
 //    the 64 lanes touch 64 different sources at every step. The i side is a
 //    running FP32 sum folded into FP64 after each group (as the tile-
-//    compensated policy); the j side of the K pairs of a lane is added with
-//    one LDS float atomic per component into the wave's own accumulator of
-//    that source -- one add per slot per step, in program order, hence a
-//    fixed order. At the end of a tile the W wave accumulators are added in
-//    wave order;
+//    compensated policy); the j-side sum of a source travels with it through
+//    the lanes (a one-lane rotation per step, DPP wave_rol, on the vector
+//    ALU), so after the 64 steps of a group it is back in the lane that
+//    owns the source, which writes it to the wave's LDS row. At the end of a
+//    tile the W wave rows are added in wave order;
 //  * item (I, I): the block on itself, i side only (each pair from both
 //    ends, the j = i term contributing 0);
 //  * every item writes FP32 partials: its i side for block I into slot J, its
@@ -54,21 +54,28 @@ struct SymFinishArgs {
     double h;
 };
 
-__device__ __forceinline__ void lds_add(float* p, float v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Lane l receives the value of lane (l + 1) mod 64 (DPP wave_rol:1).
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
 }
 
-// One tile of sources (rec[0 .. TJ)) against the K sinks of this lane.
+// One tile of sources against the K sinks of this lane. The tile is held as
+// TJ/64 groups of 64 sources, each stored twice in a row (rec[g][0..127]), so
+// that lane l meets source (l + t) mod 64 of the group at step t by reading
+// rec[g][l + t]: the step is an immediate offset of the LDS read. The j-side
+// sums of the group travel with their source, one lane down per step, so
+// after 64 steps lane l holds the sum of source l, which it stores in the
+// wave's LDS row jq[c][g*64 + l].
 template <int K, bool JSIDE>
-__device__ __forceinline__ void sym_tile(const float4* rec, float* jx, float* jy, float* jz,
-                                         const float* xi, const float* yi, const float* zi,
-                                         const float* mi, SumTile (*s)[3], float eps2, int lane) {
-    for (int g = 0; g < TJ; g += 64) {
+__device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, const float* xi,
+                                         const float* yi, const float* zi, const float* mi,
+                                         SumTile (*s)[3], float eps2, int lane) {
+    for (int g = 0; g < TJ / 64; ++g) {
+        const float4* row = rec[g] + lane;
+        float cx = 0.f, cy = 0.f, cz = 0.f;
 #pragma unroll 4
         for (int t = 0; t < 64; ++t) {
-            const int jj = g + ((lane + t) & 63);
-            const float4 q = rec[jj];
-            float cx = 0.f, cy = 0.f, cz = 0.f;
+            const float4 q = row[t];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float dx = q.x - xi[k];
@@ -89,10 +96,15 @@ __device__ __forceinline__ void sym_tile(const float4* rec, float* jx, float* jy
                 }
             }
             if (JSIDE) {
-                lds_add(jx + jj, cx);
-                lds_add(jy + jj, cy);
-                lds_add(jz + jj, cz);
+                cx = from_next_lane(cx);
+                cy = from_next_lane(cy);
+                cz = from_next_lane(cz);
             }
+        }
+        if (JSIDE) {
+            jq[g * 64 + lane] = cx;
+            jq[TJ + g * 64 + lane] = cy;
+            jq[2 * TJ + g * 64 + lane] = cz;
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -108,7 +120,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
     constexpr int NT = W * 64;
     constexpr int BI = NT * K;
     static_assert(BI % TJ == 0, "a block must hold whole tiles");
-    __shared__ float4 rec[TJ];
+    __shared__ float4 rec[TJ / 64][128];
     __shared__ float jacc[W][3][TJ];
 
     // item -> (I, J), I <= J, items ordered by J then I
@@ -137,8 +149,6 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
         s[k][1].init();
         s[k][2].init();
     }
-    float* flat = &jacc[0][0][0];
-    for (int q = tid; q < W * 3 * TJ; q += NT) flat[q] = 0.f;
 
     const int jb = J * BI;
     const int je = min(a.n, jb + BI);
@@ -147,27 +157,23 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
             const int j = jt + q;
             float4 p = make_float4(0.f, 0.f, 0.f, 0.f);  // zero-mass padding
             if (j < je) p = make_float4(float(a.x[j]), float(a.y[j]), float(a.z[j]), a.m[j]);
-            rec[q] = p;
+            rec[q >> 6][q & 63] = p;
+            rec[q >> 6][(q & 63) + 64] = p;
         }
         __syncthreads();
         if (jside)
-            sym_tile<K, true>(rec, jacc[w][0], jacc[w][1], jacc[w][2], xi, yi, zi, mi, s, a.eps2,
-                              lane);
+            sym_tile<K, true>(rec, &jacc[w][0][0], xi, yi, zi, mi, s, a.eps2, lane);
         else
-            sym_tile<K, false>(rec, nullptr, nullptr, nullptr, xi, yi, zi, mi, s, a.eps2, lane);
+            sym_tile<K, false>(rec, nullptr, xi, yi, zi, mi, s, a.eps2, lane);
         __syncthreads();
         if (jside) {
-            // j side of this tile: the wave accumulators in wave order, then
-            // cleared for the next tile (the barrier before its pair loop
-            // orders the clearing before the next adds)
+            // j side of this tile: the wave rows added in wave order (every
+            // row entry is rewritten by the next tile before it is read again)
             for (int q = tid; q < 3 * TJ; q += NT) {
                 const int c = q / TJ, jj = q - c * TJ;
                 float sum = 0.f;
 #pragma unroll
-                for (int v = 0; v < W; ++v) {
-                    sum += jacc[v][c][jj];
-                    jacc[v][c][jj] = 0.f;
-                }
+                for (int v = 0; v < W; ++v) sum += jacc[v][c][jj];
                 const int j = jt + jj;
                 if (j < je) a.part[((size_t)I * 3 + c) * a.n + j] = -sum;
             }
@@ -218,20 +224,20 @@ constexpr size_t kSymWorkspaceCap = size_t(16) << 30;
 }  // namespace
 
 SymShape choose_sym_shape(int prec, int64_t n) {
-    // Blocks of BI = W*64*K particles; at least 64 blocks (2080 equal work
-    // items, ~8 per CU) so that the triangle of block pairs balances the
-    // 256 CUs; two or more sinks per lane so that the three LDS adds of the
-    // j side are shared by several pairs.
-    SymShape s{0, 0};
-    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return s;
-    const int64_t bi = n / 64;
-    if (bi >= 4096) s = SymShape{16, 4};
-    else if (bi >= 2048) s = SymShape{8, 4};
-    else if (bi >= 1024) s = SymShape{8, 2};
-    else if (bi >= 512) s = SymShape{4, 2};
-    else s = SymShape{2, 2};
-    if (sym_partials_bytes(s, n) > kSymWorkspaceCap) return SymShape{0, 0};
-    return s;
+    // Measured on MI355X at N = 2^18 and 2^20: four-wave workgroups with four
+    // sinks per lane (blocks of 1024) are fastest -- more waves per SIMD than
+    // the larger workgroups, and one source rotation per four pairs. Blocks
+    // are kept to at most n/64 (>= 2080 equal work items for the 256 CUs),
+    // and grown only when the FP32 partials (nb * 3 * n floats) would pass
+    // the workspace cap; past the largest block the one-sided kernel is used.
+    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    static const SymShape cands[] = {{2, 2}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 256 .. 4096
+    constexpr int NC = 5;
+    auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
+    int k = 0;
+    while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 64) ++k;
+    while (k < NC && sym_partials_bytes(cands[k], n) > kSymWorkspaceCap) ++k;
+    return k < NC ? cands[k] : SymShape{0, 0};
 }
 
 size_t sym_partials_bytes(const SymShape& s, int64_t n) {
@@ -259,7 +265,7 @@ hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const 
     hipError_t e = hipErrorInvalidValue;
 #define NB_SYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_sym<WV, KV>(a, stream);
-    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(8, 2) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
 #undef NB_SYM_CASE
     if (e != hipSuccess) return e;
     SymFinishArgs f{};

@@ -57,14 +57,19 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
     # a set acting on itself with the tile-compensated policy from 16384 on:
     # the symmetric pass, one FP32 partial per particle, component and block
-    # (blocks of n/64 particles up to 4096)
+    # (blocks of min(n/64, 1024) particles, larger while the partials would
+    # pass 16 GiB)
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
-    assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 256 * 3 * (1 << 20) * 4
+    assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 1024 * 3 * (1 << 20) * 4
+    assert L.nbody_workspace_size(1, 1 << 21, TILEC) == 512 * 3 * (1 << 21) * 4
+    assert L.nbody_workspace_size(1, 3 << 20, TILEC) < 1 << 30  # one-sided kernel
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
     # and the symmetric adjoint pass: seven FP32 partials per particle and
-    # block (blocks of n/64 particles up to 2048)
+    # block (blocks of min(n/64, 512), larger while past 16 GiB, up to 2048)
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
+    assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
     assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 512 * 7 * (1 << 20) * 4
+    assert L.nbody_workspace_size(2, 1 << 21, TILEC) < 1 << 30  # one-sided kernel
 
 
 def _accel(L, ni=64, xi=A, nj=64, xj=B, mj=C, eps=0.1, G=1.0, prec=F64, acc=D, pot=None,

