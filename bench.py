@@ -57,6 +57,7 @@ CSRC = os.path.join(ROOT, "paper_2411_18889_amd", "csrc")
 KERNEL_SOURCES = {"force_kernel": ["common.h", "force.hip"],
                   "force_sym_kernel": ["common.h", "force_sym.hip"],
                   "adjoint_kernel": ["common.h", "adjoint.hip"],
+                  "adjoint_sym_kernel": ["common.h", "adjoint_sym.hip"],
                   "diffusion_kernel4": ["common.h", "diffusion.hip"]}
 
 
@@ -273,17 +274,20 @@ def main():
                 for i, k in enumerate(kinds)}
     fwd_ms = sum(a.elapsed_time(b) for a, b, _, _ in pass_events) / len(pass_events)
     adj_ms = sum(c.elapsed_time(d) for _, _, c, d in pass_events) / len(pass_events)
-    # the library's force pass for one set on itself: the symmetric
-    # (third-law) kernel for the tile-compensated policy from 16384 particles
-    # on, one pair evaluation per two interactions
-    fk = "force_sym_kernel" if (prec == "mix_tilec" and n >= 16384) else "force_kernel"
-    pairs_per_interaction = 0.5 if fk == "force_sym_kernel" else 1.0
+    # the passes the library runs here: the symmetric (third-law) kernels
+    # evaluate each pair once for two interactions
+    fpass, apass = nb.pass_info(1, n, prec), nb.pass_info(2, n, prec)
+    fk = "force_sym_kernel" if fpass["symmetric"] else "force_kernel"
+    ak = "adjoint_sym_kernel" if apass["symmetric"] else "adjoint_kernel"
+    pairs_per_interaction = 0.5 if fpass["symmetric"] else 1.0
     dom = "adjoint" if prof.ms[1] >= prof.ms[0] else "force"
     if dom == "adjoint":
-        roof = {"kernel": "adjoint_kernel (fused force + J^T lam + G^T lam)", "bound": "alu",
+        roof = {"kernel": ak + " (fused force + J^T lam + G^T lam)", "bound": "alu",
                 "achieved": adj_tflops, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": adj_tflops * 1e12 / FP32_VECTOR_PEAK,
-                "traffic": hbm_traffic("adjoint_kernel", w.name),
+                "traffic": hbm_traffic(ak, w.name),
+                "pair_evaluations_per_interaction": 0.5 if apass["symmetric"] else 1.0,
+                "shape": apass,
                 "flop_per_pair": FLOP_PER_ADJOINT_PAIR, "avg_launch_ms": a_ms}
     else:
         roof = {"kernel": fk, "bound": "alu", "achieved": force_tflops,
@@ -298,6 +302,7 @@ def main():
                   "frac_nonpacked_peak": force_tflops * 1e12 / FP32_NONPACKED_PEAK,
                   "ginteractions_per_s": float(n) * n / (f_ms * 1e-3) / 1e9,
                   "pair_evaluations_per_interaction": pairs_per_interaction,
+                  "shape": fpass,
                   "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
 
     D0 = nb.diag_dict(d0)

@@ -256,6 +256,30 @@ int nbody_profile_end(nb_profile *out);
  * NB_OP_ACCEL pass max(ni, nj). Returns 0 for an invalid op or prec. */
 size_t nbody_workspace_size(int op, int64_t n, int prec);
 
+/*
+ * nbody_pass_info -- the pair pass the library runs for n particles acting
+ * on themselves (op NB_OP_STEP: the force of a leapfrog, and of
+ * nbody_accel with xi == xj, no potential and no explicit shape; op
+ * NB_OP_ADJOINT: the fused adjoint pass of nbody_step_adjoint). Host-side
+ * only (no device needed). NB_EINVAL for another op, n outside 1..2^30 or a
+ * NULL out; NB_EUNSUPPORTED for an unknown prec.
+ *
+ * symmetric = 1: the third-law pass -- particles cut into blocks of
+ * block_particles = block * i_per_lane, one workgroup per block pair, FP32
+ * partials per block added in a fixed order (NB_MIX_TILEC from 16384
+ * particles while the partials fit a 16 GiB workspace). symmetric = 0: the
+ * one-sided kernel in the shape (i_per_lane, block, split).
+ */
+typedef struct nb_pass_info {
+    int32_t symmetric;
+    int32_t block;           /* threads per workgroup                        */
+    int32_t i_per_lane;      /* sinks per lane                               */
+    int32_t split;           /* source ranges per sink (one-sided kernel)    */
+    int64_t block_particles; /* particles per block (symmetric), else 0      */
+    size_t workspace_bytes;  /* = nbody_workspace_size(op, n, prec)          */
+} nb_pass_info;
+int nbody_pass_info(int op, int64_t n, int prec, nb_pass_info *out);
+
 /* Static text for a status code. */
 const char *nbody_strerror(int status);
 

@@ -10,5 +10,6 @@ built.
 
 from ._lib import PREC, NBodyError, nb_launch  # noqa: F401
 from .api import (accel, step, step_adjoint, diag, diag_dict, device_info, graph_cache_clear,  # noqa: F401
+                  pass_info,
                   workspace_size, pos_dtype, mass_dtype, DIAG_FIELDS)
 from .autograd import NBodyRollout, rollout  # noqa: F401

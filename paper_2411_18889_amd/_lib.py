@@ -28,6 +28,12 @@ class nb_launch(ctypes.Structure):
                 ("split", ctypes.c_int32)]
 
 
+class nb_pass_info(ctypes.Structure):
+    _fields_ = [("symmetric", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("i_per_lane", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("block_particles", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+
+
 class NBodyError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -70,9 +76,11 @@ def lib():
     L.nbody_profile_begin.argtypes = []
     L.nbody_profile_end.argtypes = [ctypes.POINTER(nb_profile_t)]
     L.nbody_graph_cache_clear.argtypes = []
+    L.nbody_pass_info.argtypes = [i32, i64, i32, ctypes.POINTER(nb_pass_info)]
     for f in ("nbody_accel", "nbody_accel_ex", "nbody_step", "nbody_step_adjoint",
               "nbody_diag", "nbody_last_hip_error", "nbody_device_info",
-              "nbody_profile_begin", "nbody_profile_end", "nbody_graph_cache_clear"):
+              "nbody_profile_begin", "nbody_profile_end", "nbody_graph_cache_clear",
+              "nbody_pass_info"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L

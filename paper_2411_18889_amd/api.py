@@ -204,3 +204,12 @@ def graph_cache_clear():
     """Free the HIP graphs that step(graph=True) cached (after their last
     launches finish)."""
     check(_lib.lib().nbody_graph_cache_clear(), "nbody_graph_cache_clear")
+
+
+def pass_info(op: int, n: int, prec: str) -> dict:
+    """The pair pass the library runs for n particles on themselves
+    (op 1 = force of a leapfrog, 2 = fused adjoint): nbody_pass_info."""
+    info = _lib.nb_pass_info()
+    check(_lib.lib().nbody_pass_info(int(op), int(n), _prec(prec), ctypes.byref(info)),
+          "nbody_pass_info")
+    return {f: getattr(info, f) for f, _ in info._fields_}

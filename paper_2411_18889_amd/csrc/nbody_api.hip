@@ -491,6 +491,38 @@ size_t nbody_workspace_size(int op, int64_t n, int prec) {
     }
 }
 
+int nbody_pass_info(int op, int64_t n, int prec, nb_pass_info* out) {
+    if (!out || n < 1 || n > kMaxN) return NB_EINVAL;
+    if (!valid_prec(prec)) return NB_EUNSUPPORTED;
+    nb_pass_info r;
+    memset(&r, 0, sizeof(r));
+    SymShape sym{0, 0};
+    Shape sh{0, 0, 0};
+    if (op == NB_OP_STEP) {
+        sym = choose_sym_shape(prec, n);
+        sh = choose_force_shape(prec, n, n);
+    } else if (op == NB_OP_ADJOINT) {
+        sym = choose_adjoint_sym_shape(prec, n);
+        sh = choose_adjoint_shape(prec, n);
+    } else {
+        return NB_EINVAL;
+    }
+    if (sym.waves) {
+        r.symmetric = 1;
+        r.block = sym.waves * 64;
+        r.i_per_lane = sym.ipl;
+        r.split = 1;
+        r.block_particles = (int64_t)sym.waves * 64 * sym.ipl;
+    } else {
+        r.block = sh.block;
+        r.i_per_lane = sh.ipl;
+        r.split = sh.split;
+    }
+    r.workspace_bytes = nbody_workspace_size(op, n, prec);
+    *out = r;
+    return NB_OK;
+}
+
 const char* nbody_strerror(int status) {
     switch (status) {
     case NB_OK: return "success";

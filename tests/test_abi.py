@@ -173,3 +173,20 @@ def test_diffusion_validation(L):
     assert step(f=None) == NB_EINVAL
     assert step(fn=P(0x200002)) == NB_EINVAL                  # misaligned
     assert step(fn=P(0x100000 + 64)) == NB_EINVAL              # overlaps f
+
+
+def test_pass_info(L):
+    from paper_2411_18889_amd import _lib
+    info = _lib.nb_pass_info()
+    assert L.nbody_pass_info(1, 1 << 20, TILEC, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
+    assert info.workspace_bytes == L.nbody_workspace_size(1, 1 << 20, TILEC)
+    assert L.nbody_pass_info(2, 1 << 20, TILEC, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 1024, 2, 2048)
+    assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
+    assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
+    assert L.nbody_pass_info(1, 1000, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
+    assert L.nbody_pass_info(0, 1000, TILEC, ctypes.byref(info)) == NB_EINVAL
+    assert L.nbody_pass_info(1, 0, TILEC, ctypes.byref(info)) == NB_EINVAL
+    assert L.nbody_pass_info(1, 1000, 17, ctypes.byref(info)) == NB_EUNSUPPORTED
+    assert L.nbody_pass_info(1, 1000, TILEC, None) == NB_EINVAL
