@@ -32,7 +32,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12      # MI355X published FP32 vector peak (counts packed FP32)
-FP32_NONPACKED_PEAK = 78.6e12    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FLOP_PER_FORCE_PAIR = 20         # 3 sub + 3 FMA + 3 mul + 3 FMA (FMA = 2) + 2 for rsqrt
 FLOP_PER_ADJOINT_PAIR = 55       # count of the fused adjoint pair body, same convention
 
@@ -299,7 +298,6 @@ def main():
                   "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                   "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK,
                   "traffic": hbm_traffic(fk, w.name),
-                  "frac_nonpacked_peak": force_tflops * 1e12 / FP32_NONPACKED_PEAK,
                   "ginteractions_per_s": float(n) * n / (f_ms * 1e-3) / 1e9,
                   "pair_evaluations_per_interaction": pairs_per_interaction,
                   "shape": fpass,

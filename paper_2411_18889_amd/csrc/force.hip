@@ -18,6 +18,8 @@
 //    adds them in a fixed order: no atomics, bitwise reproducible;
 //  * the sum over sources includes j = i, which adds exactly 0 to a_i (d = 0)
 //    and m_i / eps to the potential sum; that term is removed at the end.
+#include <algorithm>
+
 #include "common.h"
 
 namespace nb {
@@ -255,25 +257,36 @@ size_t force_partials_bytes(const Shape& s, int64_t ni) {
 }
 
 Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
-    // Measured on MI355X (launch-shape sweeps at N = 2^14 .. 2^20):
-    //  * FP32 pair arithmetic: 2 sinks per lane; 512-lane workgroups (fewer
-    //    barriers per pair) from 65536 sinks up, 128 below;
+    // Measured on MI355X (launch-shape sweeps at N = 2^10 .. 2^20):
+    //  * FP32 pair arithmetic: 1 sink per lane in 256-lane workgroups up to
+    //    12288 sinks, then 2 sinks per lane, 128-lane workgroups, and
+    //    512-lane ones (fewer barriers per pair) from 65536 sinks up;
+    //  * FP64: 64-lane workgroups below 65536 sinks (1 sink per lane below
+    //    3072, else 4), 256 lanes above;
     //  * many more workgroups than the chip holds at once balance the CUs
     //    better even when one round would already fill every SIMD: split the
-    //    source range until there are ~64K wavefronts (8 ranges at 2^20,
-    //    32 at 2^18, 5-16 % faster), keeping every range >= 4 tiles long.
+    //    source range until there are ~64K wavefronts (8 ranges at 2^20, 32
+    //    at 2^18, 5-16 % faster), keeping every range >= 4 tiles long (8
+    //    for the 64-lane FP64 shape) -- or, below 16384 sources, as short as
+    //    one tile, up to 32 ranges (64 in FP64): 6x faster at N = 1024 in
+    //    FP64, 2.6x at 4096 in FP32, where the pass is otherwise a handful
+    //    of workgroups.
     Shape s;
     if (prec == NB_F64) {
-        s = Shape{1, 256, 1};
+        s = ni < 3072 ? Shape{1, 64, 1} : (ni < 65536 ? Shape{4, 64, 1} : Shape{1, 256, 1});
     } else {
-        s = Shape{2, ni >= 65536 ? 512 : 128, 1};
+        s = ni <= 12288 ? Shape{1, 256, 1} : Shape{2, ni >= 65536 ? 512 : 128, 1};
     }
     const int64_t groups = (ni + (int64_t)s.block * s.ipl - 1) / ((int64_t)s.block * s.ipl);
     const int64_t waves = groups * (s.block / 64);
     const int64_t want = 65536;
     int64_t split = (want + waves - 1) / waves;
-    const int64_t max_by_tiles = nj / (4 * (int64_t)s.block);
-    if (split > max_by_tiles) split = max_by_tiles;
+    const int64_t min_tiles = (prec == NB_F64 && s.block == 64) ? 8 : 4;
+    const int64_t long_ranges = nj / (min_tiles * (int64_t)s.block);
+    const int64_t short_ranges =
+        nj < 16384 ? std::min<int64_t>(prec == NB_F64 ? 64 : 32, nj / (int64_t)s.block) : 0;
+    const int64_t max_ranges = std::max(long_ranges, short_ranges);
+    if (split > max_ranges) split = max_ranges;
     if (split > 256) split = 256;
     if (split < 1) split = 1;
     s.split = (int)split;

@@ -56,7 +56,7 @@ def tune(n, prec, eps=2.0 ** -8, shapes=None, reps=None, seed=5):
     t_lib = _time(lambda: api.accel(X, M, eps, prec=prec), reps)
     if shapes is None:
         splits = sorted({1, 2, 4, 8, 16, 32, 64, 128} | {max(1, min(256, (4096 * 64) // max(1, n)))})
-        shapes = list(itertools.product((1, 2, 4), (128, 256, 512, 1024), splits))
+        shapes = list(itertools.product((1, 2, 4), (64, 128, 256, 512, 1024), splits))
     best = None
     rows = []
     for ipl, block, split in shapes:

@@ -1,6 +1,6 @@
 """GPU parity of the symmetric (third-law) force pass, which the library
 uses for one set acting on itself with the tile-compensated FP32 policy from
-16384 particles on: blocks of min(n/64, 1024) particles (2048 and 4096 when
+32768 particles on: blocks of min(n/64, 1024) particles (2048 and 4096 when
 the partials would pass 16 GiB), a work item per block pair, FP32 partials
 per block added in a fixed order.
 
@@ -22,8 +22,8 @@ pytestmark = pytest.mark.gpu
 PREC = "mix_tilec"
 TOL = 1e-5
 
-# block sizes 256 (16384 .. 32767), 512, 1024, 2048; ragged last blocks and tiles
-SYM_NS = (16384, 16385, 16384 + 255, 20000, 32767, 32768, 40000, 65536 + 1000, 131072 + 77)
+# blocks of 512 (32768 .. 65535) and 1024; ragged last blocks and tiles
+SYM_NS = (32768, 32769, 32768 + 255, 40000, 65535, 65536, 65536 + 1000, 131072 + 77)
 
 
 def _classic(xd, md, eps):
@@ -39,7 +39,7 @@ def test_sym_matches_oracle_and_one_sided(n):
     xd, _, md = to_dev(x, v, m, PREC)
     a = host(nb.accel(xd, md, eps, prec=PREC))
     xs, ms = host(xd), host(md)
-    if n <= 20000:
+    if n <= 40000:
         ref = oracle.accel(xs, ms, eps)
         e = rel(a, ref)
     else:
@@ -75,7 +75,7 @@ def test_sym_two_clusters_far_apart():
     an O(1) error in the clumps' mutual attraction. The oracle gets the
     positions as the kernel's FP32 rounding leaves them, so that the
     rounding of positions far from the origin is not counted as error."""
-    n = 16384 + 512
+    n = 32768 + 512
     x1, v1, m1 = plummer_sphere(n // 2, 221)
     x2, v2, m2 = plummer_sphere(n - n // 2, 222)
     x2 = x2 + np.array([[20.0], [0.0], [0.0]])
@@ -98,9 +98,9 @@ def test_sym_two_clusters_far_apart():
 
 
 def test_sym_step_matches_oracle():
-    """The leapfrog at n = 16384 (symmetric force with the closing half-kick
+    """The leapfrog at n = 32768 (symmetric force with the closing half-kick
     in its finishing kernel) against the oracle's FP64 steps."""
-    n, S = 16384, 3
+    n, S = 32768, 3
     x, v, m = plummer_sphere(n, 230)
     eps, dt = 2.0 ** -7, 2.0 ** -8
     xd, vd, md = to_dev(x, v, m, PREC)
