@@ -51,7 +51,8 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1000, 17) == 0         # unknown precision
     assert L.nbody_workspace_size(0, 0, F64) == 0           # n < 1
     assert L.nbody_workspace_size(3, 1000, F64) > 0         # diagnostics always need some
-    assert L.nbody_workspace_size(0, 1024, F64) == 0        # one source range: no partials
+    assert L.nbody_workspace_size(0, 64, F64) == 0          # one source tile: no partials
+    assert L.nbody_workspace_size(0, 1024, F64) > 0         # small N: short source ranges
     assert L.nbody_workspace_size(0, 4096, TILEC) > 0       # split source ranges: partials
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) > 0
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
