@@ -43,9 +43,11 @@ struct ASymFinishArgs {
     double* gm;
 };
 
-// Lane l receives the value of lane (l + 1) mod 64 (DPP wave_rol:1).
+// Lane l receives the value of lane (l + 1) mod 64, through the LDS
+// crossbar (ds_bpermute; see the force pass).
 __device__ __forceinline__ float from_next_lane(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
+    const int src = ((__lane_id() + 1) & 63) << 2;  // byte address of the source lane
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
 }
 
 template <int K, bool JSIDE>

@@ -17,10 +17,10 @@
 //    the 64 lanes touch 64 different sources at every step. The i side is a
 //    running FP32 sum folded into FP64 after each group (as the tile-
 //    compensated policy); the j-side sum of a source travels with it through
-//    the lanes (a one-lane rotation per step, DPP wave_rol, on the vector
-//    ALU), so after the 64 steps of a group it is back in the lane that
-//    owns the source, which writes it to the wave's LDS row. At the end of a
-//    tile the W wave rows are added in wave order;
+//    the lanes (a one-lane rotation per step through the LDS crossbar), so
+//    after the 64 steps of a group it is back in the lane that owns the
+//    source, which writes it to the wave's LDS row. At the end of a tile the
+//    W wave rows are added in wave order;
 //  * item (I, I): the block on itself, i side only (each pair from both
 //    ends, the j = i term contributing 0);
 //  * every item writes FP32 partials: its i side for block I into slot J, its
@@ -54,9 +54,14 @@ struct SymFinishArgs {
     double h;
 };
 
-// Lane l receives the value of lane (l + 1) mod 64 (DPP wave_rol:1).
+// Lane l receives the value of lane (l + 1) mod 64, through the LDS
+// crossbar (ds_bpermute): measured 14 % faster for the force pass and 10 %
+// for the adjoint than the same rotation on the vector ALU (DPP wave_rol:1),
+// whose moves cost about four VALU issue slots each and sit in the
+// accumulation chains; the crossbar is otherwise idle here.
 __device__ __forceinline__ float from_next_lane(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xF, 0xF, false));
+    const int src = ((__lane_id() + 1) & 63) << 2;  // byte address of the source lane
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
 }
 
 // One tile of sources against the K sinks of this lane. The tile is held as
