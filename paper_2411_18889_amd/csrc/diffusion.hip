@@ -77,8 +77,8 @@ __global__ __launch_bounds__(TK * TJ) void diffusion_kernel(int nx, int ny, int 
 // LDS row layout: [.., left halo at V_OFF - 1, 256 points at V_OFF.., right
 // halo] with V_OFF = 4 so each lane's 4 points are 16-byte aligned.
 constexpr int TK4 = 256;
-constexpr int TJ4 = 8;
-constexpr int CI4 = 32;
+constexpr int TJ4 = 16;
+constexpr int CI4 = 64;
 constexpr int V_OFF = 4;
 constexpr int ROW = TK4 + 2 * V_OFF;
 

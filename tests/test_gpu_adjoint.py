@@ -167,3 +167,26 @@ def test_position_adjoint_sum_invariant_on_gpu(n):
     assert np.all(np.abs(dlx.sum(axis=1)) <= 1e-5 * scale), (dlx.sum(axis=1), scale)
     expect_lv = lv0.sum(axis=1) + S * dt * lx0.sum(axis=1)
     assert np.all(np.abs(host(lv).sum(axis=1) - expect_lv) <= 1e-5 * S * dt * scale + 1e-9)
+
+
+def test_adjoint_symmetric_pass_bitwise_reproducible():
+    """The symmetric adjoint pass sums in a fixed order (no atomics): the
+    same walk twice gives bitwise the same adjoints and state."""
+    n, S = 40000, 2
+    x, v, m, _ = _problem(n, 97)
+    eps, dt = 2.0 ** -8, 2.0 ** -9
+    xd, vd, md = to_dev(x, v, m, "mix_tilec")
+    acc = torch.empty_like(xd)
+    nb.step(xd, vd, md, acc, eps, dt, S, prec="mix_tilec")
+    lam = torch.tensor(np.random.default_rng(5).normal(size=(3, n)), device=DEV)
+    outs = []
+    for _ in range(2):
+        st = [t.clone() for t in (xd, vd, acc)]
+        lx, lv = lam.clone(), torch.zeros_like(lam)
+        lm = torch.zeros(n, dtype=torch.float64, device=DEV)
+        nb.step_adjoint(st[0], st[1], md, st[2], lx, lv, lm, eps, dt, S, prec="mix_tilec",
+                        entry_half=True)
+        outs.append((lx, lv, lm, st[0], st[1]))
+    assert nb.pass_info(2, n, "mix_tilec")["symmetric"] == 1
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)

@@ -14,9 +14,9 @@ from tests.gpu_util import DEV, to_dev
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec", ("mix_tilec", "f32"))
-def test_captured_steps_replay_bitwise(prec):
-    n, S, eps, dt = 16384, 5, 2.0 ** -7, 2.0 ** -8
+@pytest.mark.parametrize("prec,n", [("mix_tilec", 16384), ("f32", 16384), ("mix_tilec", 40000)])
+def test_captured_steps_replay_bitwise(prec, n):
+    S, eps, dt = 5, 2.0 ** -7, 2.0 ** -8
     x, v, m = plummer_sphere(n, 60)
     x0, v0, md = to_dev(x, v, m, prec)
 
@@ -60,7 +60,7 @@ def _reference(x0, v0, md, eps, dt, S, prec, ckpt_every):
 
 
 @pytest.mark.parametrize("prec,n", [("f64", 1024), ("mix_tilec", 16384), ("f32", 4096),
-                                    ("mix_kahan", 300)])
+                                    ("mix_kahan", 300), ("mix_tilec", 40000)])
 @pytest.mark.parametrize("side_stream", (False, True))
 def test_library_graph_replays_bitwise(prec, n, side_stream):
     """NB_GRAPH: the library records the loop once, then relaunches the cached
