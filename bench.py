@@ -60,6 +60,31 @@ KERNEL_SOURCES = {"force_kernel": ["common.h", "force.hip"],
                   "diffusion_kernel4": ["common.h", "diffusion.hip"]}
 
 
+def gpu_clocks():
+    """Current shader clock (MHz) and power cap (W) of the first AMD GPU from
+    sysfs, best effort: {} when the files are not readable."""
+    import glob
+    out = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        try:
+            with open(dev + "/vendor") as fh:
+                if fh.read().strip() != "0x1002":
+                    continue
+            with open(dev + "/pp_dpm_sclk") as fh:
+                cur = [ln for ln in fh.read().splitlines() if ln.strip().endswith("*")]
+            if cur:
+                out["sclk_mhz"] = float(cur[0].split(":")[1].strip().rstrip("*").strip().lower().rstrip("mhz"))
+            caps = glob.glob(dev + "/hwmon/hwmon*/power1_cap")
+            if caps:
+                with open(caps[0]) as fh:
+                    out["power_cap_w"] = int(fh.read().strip()) / 1e6
+        except (OSError, ValueError, IndexError):
+            continue
+        if out:
+            break
+    return out
+
+
 def kernel_source_hash(kernel):
     import hashlib
     h = hashlib.sha256()
@@ -366,6 +391,7 @@ def main():
         "adjoint_over_forward_kernel": a_ms / f_ms,
         "force_rel_err_sampled": rel_err,
         "energy_drift": dE,
+        "gpu_clocks_after_run": gpu_clocks(),
         "per_kind": per_kind,
         "cpu_baseline": cpu,
     }
