@@ -6,8 +6,10 @@
 //   to i:  m_j s^-3/2 d,   T(d) u,    s^-3/2 (lam_j . d)
 //   to j: -m_i s^-3/2 d,  -T(d) u,   -s^-3/2 (lam_i . d)
 // (T is even in d and u is odd under the swap), so one reciprocal square
-// root, one T(d) u and one s^-3/2 serve both ends: 44 VALU + 1 rsqrt per
-// pair, i.e. 22 VALU + 1/2 rsqrt per interaction against 34 + 1 one-sided.
+// root, one T(d) u and one s^-3/2 serve both ends: 43 VALU + 1 rsqrt per
+// pair (d . u comes from the two dot products with lam_i and lam_j, which
+// the mass adjoints need anyway), i.e. 21.5 VALU + 1/2 rsqrt per
+// interaction against 34 + 1 one-sided.
 // The blocking, the work items (block pairs I <= J), the source-side sums
 // carried through the lanes and the fixed-order FP32 partials are those of
 // the symmetric force pass, with seven quantities instead of three:
@@ -85,7 +87,14 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
                 const float ux = fmat(mi[k], lj.x, -(q.w * lxi[k]));
                 const float uy = fmat(mi[k], lj.y, -(q.w * lyi[k]));
                 const float uz = fmat(mi[k], lj.z, -(q.w * lzi[k]));
-                const float du = fmat(dz, uz, fmat(dy, uy, dx * ux));
+                const float dl = fmat(dz, lj.z, fmat(dy, lj.y, dx * lj.x));  // d . lam_j
+                float du, dli = 0.f;
+                if (JSIDE) {  // d . u = m_i (d . lam_j) - m_j (d . lam_i), both dots needed anyway
+                    dli = fmat(dz, lzi[k], fmat(dy, lyi[k], dx * lxi[k]));
+                    du = fmat(mi[k], dl, -(q.w * dli));
+                } else {
+                    du = fmat(dz, uz, fmat(dy, uy, dx * ux));
+                }
                 const float e = (-3.f * r2) * du;
                 const float tx = fmat(e, dx, ux);
                 const float ty = fmat(e, dy, uy);
@@ -93,7 +102,6 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
                 s[k][3].add_fma(r3, tx);
                 s[k][4].add_fma(r3, ty);
                 s[k][5].add_fma(r3, tz);
-                const float dl = fmat(dz, lj.z, fmat(dy, lj.y, dx * lj.x));
                 s[k][6].add_fma(r3, dl);
                 if (JSIDE) {
                     const float wi = r3 * mi[k];
@@ -103,7 +111,6 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
                     c[3] = fmat(r3, tx, c[3]);
                     c[4] = fmat(r3, ty, c[4]);
                     c[5] = fmat(r3, tz, c[5]);
-                    const float dli = fmat(dz, lzi[k], fmat(dy, lyi[k], dx * lxi[k]));
                     c[6] = fmat(r3, dli, c[6]);
                 }
             }
