@@ -52,7 +52,15 @@ __device__ __forceinline__ float from_next_lane(float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
 }
 
-template <int K, bool JSIDE>
+// F: also accumulate the force a (quantities 0..2); without it (a pass whose
+// state comes from a checkpoint, not from walking back) the quantities are
+// 3..6 only: 8 VALU, three rotations and three partial rows less per pair.
+template <bool F> struct QRange {
+    static constexpr int lo = F ? 0 : 3;  // first quantity accumulated
+    static constexpr int n = NQ - lo;     // partial rows per block
+};
+
+template <int K, bool JSIDE, bool F>
 __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 (*rl)[128], float* jq,
                                           const float* xi, const float* yi, const float* zi,
                                           const float* mi, const float* lxi, const float* lyi,
@@ -64,9 +72,10 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
         const float4* rowp = rp[g] + lane;
         const float4* rowl = rl[g] + lane;
         // j-side sums of the group's sources, carried one lane down per step
+        constexpr int Q0 = QRange<F>::lo;
         float c[NQ];
 #pragma unroll
-        for (int p = 0; p < NQ; ++p) c[p] = 0.f;
+        for (int p = Q0; p < NQ; ++p) c[p] = 0.f;
 #pragma unroll 2
         for (int t = 0; t < 64; ++t) {
             const float4 q = rowp[t];
@@ -80,10 +89,12 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
                 const float r = rsqrt_pair(ss);
                 const float r2 = r * r;
                 const float r3 = r2 * r;
-                const float wj = r3 * q.w;
-                s[k][0].add_fma(dx, wj);
-                s[k][1].add_fma(dy, wj);
-                s[k][2].add_fma(dz, wj);
+                if (F) {
+                    const float wj = r3 * q.w;
+                    s[k][0].add_fma(dx, wj);
+                    s[k][1].add_fma(dy, wj);
+                    s[k][2].add_fma(dz, wj);
+                }
                 const float ux = fmat(mi[k], lj.x, -(q.w * lxi[k]));
                 const float uy = fmat(mi[k], lj.y, -(q.w * lyi[k]));
                 const float uz = fmat(mi[k], lj.z, -(q.w * lzi[k]));
@@ -104,10 +115,12 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
                 s[k][5].add_fma(r3, tz);
                 s[k][6].add_fma(r3, dl);
                 if (JSIDE) {
-                    const float wi = r3 * mi[k];
-                    c[0] = fmat(dx, wi, c[0]);
-                    c[1] = fmat(dy, wi, c[1]);
-                    c[2] = fmat(dz, wi, c[2]);
+                    if (F) {
+                        const float wi = r3 * mi[k];
+                        c[0] = fmat(dx, wi, c[0]);
+                        c[1] = fmat(dy, wi, c[1]);
+                        c[2] = fmat(dz, wi, c[2]);
+                    }
                     c[3] = fmat(r3, tx, c[3]);
                     c[4] = fmat(r3, ty, c[4]);
                     c[5] = fmat(r3, tz, c[5]);
@@ -116,22 +129,23 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
             }
             if (JSIDE) {
 #pragma unroll
-                for (int p = 0; p < NQ; ++p) c[p] = from_next_lane(c[p]);
+                for (int p = Q0; p < NQ; ++p) c[p] = from_next_lane(c[p]);
             }
         }
         if (JSIDE) {  // back in the lane that owns the source
 #pragma unroll
-            for (int p = 0; p < NQ; ++p) jq[p * TJ + g * 64 + lane] = c[p];
+            for (int p = Q0; p < NQ; ++p) jq[p * TJ + g * 64 + lane] = c[p];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int p = 0; p < NQ; ++p) s[k][p].tile_end();
+            for (int p = Q0; p < NQ; ++p) s[k][p].tile_end();
     }
 }
 
-template <int W, int K>
+template <int W, int K, bool F>
 __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
+    constexpr int Q0 = QRange<F>::lo, NQF = QRange<F>::n;
     constexpr int NT = W * 64;
     constexpr int BI = NT * K;
     static_assert(BI % TJ == 0, "a block must hold whole tiles");
@@ -164,7 +178,7 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         lyi[k] = ok ? float(a.ly[i]) : 0.f;
         lzi[k] = ok ? float(a.lz[i]) : 0.f;
 #pragma unroll
-        for (int p = 0; p < NQ; ++p) s[k][p].init();
+        for (int p = Q0; p < NQ; ++p) s[k][p].init();
     }
 
     const int jb = J * BI;
@@ -185,19 +199,19 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         }
         __syncthreads();
         if (jside)
-            asym_tile<K, true>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2,
-                               lane);
+            asym_tile<K, true, F>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, lxi, lyi, lzi, s,
+                                  a.eps2, lane);
         else
-            asym_tile<K, false>(rp, rl, nullptr, xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2, lane);
+            asym_tile<K, false, F>(rp, rl, nullptr, xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2, lane);
         __syncthreads();
         if (jside) {
-            for (int q = tid; q < NQ * TJ; q += NT) {
-                const int p = q / TJ, jj = q - p * TJ;
+            for (int q = tid; q < NQF * TJ; q += NT) {
+                const int r = q / TJ, jj = q - r * TJ;  // partial row r = quantity Q0 + r
                 float sum = 0.f;
 #pragma unroll
-                for (int v = 0; v < W; ++v) sum += jacc[v][p][jj];
+                for (int v = 0; v < W; ++v) sum += jacc[v][Q0 + r][jj];
                 const int j = jt + jj;
-                if (j < je) a.part[((size_t)I * NQ + p) * a.n + j] = -sum;
+                if (j < je) a.part[((size_t)I * NQF + r) * a.n + j] = -sum;
             }
         }
     }
@@ -206,29 +220,31 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         const int i = ibase + k * 64;
         if (i >= a.n) continue;
 #pragma unroll
-        for (int p = 0; p < NQ; ++p)
-            a.part[((size_t)J * NQ + p) * a.n + i] = float(s[k][p].total());
+        for (int p = Q0; p < NQ; ++p)
+            a.part[((size_t)J * NQF + (p - Q0)) * a.n + i] = float(s[k][p].total());
     }
 }
 
 // Slot-ordered FP64 sum of the partials, then the reverse-walk epilogue:
 //   lam_x += c G J^T lam;  lam_m += c (-G) G^T-sum;
-//   if update_state: acc = G a_sum; v <- v - h acc.
+//   if update_state (F): acc = G a_sum; v <- v - h acc.
+template <bool F>
 __global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs a) {
+    constexpr int Q0 = QRange<F>::lo, NQF = QRange<F>::n;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     double q[NQ] = {0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < a.nb; ++k) {
-        const float* p = a.part + (size_t)k * NQ * a.n + i;
+        const float* p = a.part + (size_t)k * NQF * a.n + i;
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) q[c] += double(p[(size_t)c * a.n]);
+        for (int c = Q0; c < NQ; ++c) q[c] += double(p[(size_t)(c - Q0) * a.n]);
     }
     const double G = a.G, c = a.c;
     a.gx[i] = a.gx[i] + c * (G * q[3]);
     a.gy[i] = a.gy[i] + c * (G * q[4]);
     a.gz[i] = a.gz[i] + c * (G * q[5]);
     a.gm[i] = a.gm[i] + c * (-G * q[6]);
-    if (a.update_state) {
+    if (F) {
         const double ax = G * q[0], ay = G * q[1], az = G * q[2];
         a.ax[i] = ax;
         a.ay[i] = ay;
@@ -240,10 +256,14 @@ __global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs 
 }
 
 template <int W, int K>
-hipError_t launch_asym(const ASymArgs& a, hipStream_t stream) {
+hipError_t launch_asym(const ASymArgs& a, bool force, hipStream_t stream) {
     const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
-    hipLaunchKernelGGL((adjoint_sym_kernel<W, K>), dim3((unsigned)items), dim3(W * 64), 0, stream,
-                       a);
+    if (force)
+        hipLaunchKernelGGL((adjoint_sym_kernel<W, K, true>), dim3((unsigned)items), dim3(W * 64), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((adjoint_sym_kernel<W, K, false>), dim3((unsigned)items), dim3(W * 64),
+                           0, stream, a);
     return hipGetLastError();
 }
 
@@ -299,7 +319,7 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     a.part = static_cast<float*>(ws);
     hipError_t e = hipErrorInvalidValue;
 #define NB_ASYM_CASE(WV, KV) \
-    if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, stream);
+    if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, update_state, stream);
     NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(16, 2)
 #undef NB_ASYM_CASE
     if (e != hipSuccess) return e;
@@ -310,7 +330,7 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     f.G = G;
     f.c = c;
     f.h = h;
-    f.update_state = update_state ? 1 : 0;
+    f.update_state = update_state ? 1 : 0;  // also selects the kernels' force accumulation
     double* pa = static_cast<double*>(acc);
     double* pv = static_cast<double*>(v);
     double* pg = static_cast<double*>(lam_x);
@@ -318,8 +338,12 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     f.vx = pv; f.vy = pv + n; f.vz = pv + 2 * n;
     f.gx = pg; f.gy = pg + n; f.gz = pg + 2 * n;
     f.gm = lam_m;
-    hipLaunchKernelGGL(adjoint_sym_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                       stream, f);
+    if (update_state)
+        hipLaunchKernelGGL(adjoint_sym_finish_kernel<true>, dim3((unsigned)((n + 255) / 256)),
+                           dim3(256), 0, stream, f);
+    else
+        hipLaunchKernelGGL(adjoint_sym_finish_kernel<false>, dim3((unsigned)((n + 255) / 256)),
+                           dim3(256), 0, stream, f);
     return hipGetLastError();
 }
 
