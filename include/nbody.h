@@ -266,7 +266,7 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
  *
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair, FP32
- * partials per block added in a fixed order (NB_MIX_TILEC from 32768
+ * partials per block added in a fixed order (NB_MIX_TILEC from 16384
  * particles while the partials fit a 16 GiB workspace). symmetric = 0: the
  * one-sided kernel in the shape (i_per_lane, block, split).
  */

@@ -278,11 +278,11 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // and grown, with more waves per workgroup, while the FP32 partials
     // (nb * 7 * n floats) would pass the workspace cap (blocks of 2048 at
     // 2^20); past the largest block the one-sided kernel is used.
-    // Below 32768 particles the one-sided kernel is as fast or faster
-    // (measured: 1 % slower at 16384, 6 % faster at 24576, 12 % at 32768).
-    if (prec != NB_MIX_TILEC || n < 64 * 512 || n > (int64_t(1) << 28)) return SymShape{0, 0};
-    static const SymShape cands[] = {{4, 2}, {8, 2}, {16, 2}};  // 512 .. 2048
-    constexpr int NC = 3;
+    // Below 16384 particles the one-sided kernel is as fast (measured: 3 %
+    // slower at 12288, 11 % faster at 16384, 21 % at 24576).
+    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    static const SymShape cands[] = {{2, 2}, {4, 2}, {8, 2}, {16, 2}};  // 256 .. 2048
+    constexpr int NC = 4;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 512 && bi(cands[k + 1]) <= n / 64) ++k;
@@ -320,7 +320,7 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     hipError_t e = hipErrorInvalidValue;
 #define NB_ASYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, update_state, stream);
-    NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(16, 2)
+    NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(16, 2)
 #undef NB_ASYM_CASE
     if (e != hipSuccess) return e;
     ASymFinishArgs f{};

@@ -232,17 +232,17 @@ SymShape choose_sym_shape(int prec, int64_t n) {
     // Measured on MI355X at N = 2^18 and 2^20: four-wave workgroups with four
     // sinks per lane (blocks of 1024) are fastest -- more waves per SIMD than
     // the larger workgroups, and one source rotation per four pairs. Blocks
-    // are kept to at most n/64 (>= 2080 equal work items for the 256 CUs),
+    // are kept to at most n/48 (>= 1176 equal work items for the 256 CUs),
     // and grown only when the FP32 partials (nb * 3 * n floats) would pass
     // the workspace cap; past the largest block the one-sided kernel is used.
-    // Below 32768 particles the one-sided kernel is as fast or faster
-    // (measured: 3 % slower at 16384, equal at 24576, 9 % faster at 32768).
-    if (prec != NB_MIX_TILEC || n < 64 * 512 || n > (int64_t(1) << 28)) return SymShape{0, 0};
-    static const SymShape cands[] = {{4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 512 .. 4096
-    constexpr int NC = 4;
+    // Below 16384 particles the one-sided kernel is as fast (measured: 6 %
+    // slower at 12288, 10 % faster at 16384, 37 % at 24576).
+    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    static const SymShape cands[] = {{2, 2}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 256 .. 4096
+    constexpr int NC = 5;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
-    while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 64) ++k;
+    while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48) ++k;
     while (k < NC && sym_partials_bytes(cands[k], n) > kSymWorkspaceCap) ++k;
     return k < NC ? cands[k] : SymShape{0, 0};
 }
@@ -272,7 +272,7 @@ hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const 
     hipError_t e = hipErrorInvalidValue;
 #define NB_SYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_sym<WV, KV>(a, stream);
-    NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
 #undef NB_SYM_CASE
     if (e != hipSuccess) return e;
     SymFinishArgs f{};

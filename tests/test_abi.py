@@ -56,10 +56,12 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 4096, TILEC) > 0       # split source ranges: partials
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) > 0
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
-    # a set acting on itself with the tile-compensated policy from 32768 on:
+    # a set acting on itself with the tile-compensated policy from 16384 on:
     # the symmetric pass, one FP32 partial per particle, component and block
-    # (blocks of min(n/64, 1024) particles, larger while the partials would
-    # pass 16 GiB)
+    # (blocks of at most min(n/48, 1024) particles, larger while the partials
+    # would pass 16 GiB)
+    assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
+    assert L.nbody_workspace_size(1, 24576, TILEC) == 48 * 3 * 24576 * 4
     assert L.nbody_workspace_size(1, 32768, TILEC) == 64 * 3 * 32768 * 4
     assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 1024 * 3 * (1 << 20) * 4
     assert L.nbody_workspace_size(1, 1 << 21, TILEC) == 512 * 3 * (1 << 21) * 4
@@ -67,6 +69,7 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
     # and the symmetric adjoint pass: seven FP32 partials per particle and
     # block (blocks of min(n/64, 512), larger while past 16 GiB, up to 2048)
+    assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
     assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
     assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 512 * 7 * (1 << 20) * 4
