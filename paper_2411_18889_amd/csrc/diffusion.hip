@@ -74,8 +74,11 @@ __global__ __launch_bounds__(TK * TJ) void diffusion_kernel(int nx, int ny, int 
 // (16-byte loads and stores), a wave covers 256 k points of one row, a
 // workgroup TJ4 rows; the plane two steps ahead is already in flight while
 // the current one is computed, so each wave keeps 2 KB of loads outstanding.
-// LDS row layout: [.., left halo at V_OFF - 1, 256 points at V_OFF.., right
-// halo] with V_OFF = 4 so each lane's 4 points are 16-byte aligned.
+// The j +- 1 rows go through LDS (row layout [.., 256 points at V_OFF..] with
+// V_OFF = 4 so each lane's 4 points are a 16-byte access); the k +- 1
+// neighbours of a lane's 4 points are the adjacent lanes' end points, taken
+// with DPP wave shifts -- reading them from LDS at a 4-float stride cost
+// 4-way bank conflicts (a third of the LDS cycles) and 6-9 % at 512^3.
 constexpr int TK4 = 256;
 constexpr int TJ4 = 16;
 constexpr int CI4 = 64;
@@ -115,8 +118,11 @@ __global__ __launch_bounds__(64 * TJ4) void diffusion_kernel4(int nx, int ny, in
         const float4 after = load_row4(f, (int64_t)min(i + 2, nx - 1) * plane + row, k0, nz);
         __syncthreads();  // the previous plane has been read by every lane
         *reinterpret_cast<float4*>(&pl[ty + 1][V_OFF + 4 * lane]) = cur;
-        if (lane == 0) pl[ty + 1][V_OFF - 1] = f[base + row + max(kl, 0)];
-        if (lane == 63) pl[ty + 1][V_OFF + TK4] = f[base + row + min(kr, nz - 1)];
+        // k neighbours across lanes come from the adjacent lanes (DPP wave
+        // shifts); the tile's two halo points, needed by lanes 0 and 63 only,
+        // are read by the whole wave from one address each
+        const float hl = f[base + row + max(kl, 0)];
+        const float hr = f[base + row + min(kr, nz - 1)];
         if (ty == 0) {
             *reinterpret_cast<float4*>(&pl[0][V_OFF + 4 * lane]) = load_row4(f, base + row_jm, k0, nz);
         }
@@ -127,8 +133,10 @@ __global__ __launch_bounds__(64 * TJ4) void diffusion_kernel4(int nx, int ny, in
         if (store) {
             const float4 jp = *reinterpret_cast<const float4*>(&pl[ty + 2][V_OFF + 4 * lane]);
             const float4 jm = *reinterpret_cast<const float4*>(&pl[ty][V_OFF + 4 * lane]);
-            const float km0 = pl[ty + 1][V_OFF + 4 * lane - 1];
-            const float kp3 = pl[ty + 1][V_OFF + 4 * lane + 4];
+            const float km0 = __int_as_float(__builtin_amdgcn_update_dpp(
+                __float_as_int(hl), __float_as_int(cur.w), 0x138, 0xF, 0xF, false));  // lane - 1
+            const float kp3 = __int_as_float(__builtin_amdgcn_update_dpp(
+                __float_as_int(hr), __float_as_int(cur.x), 0x130, 0xF, 0xF, false));  // lane + 1
             // the last point of the grid has itself as its k+1 neighbour
             const float kp3c = (k0 + 4 < nz) ? kp3 : cur.w;
             const float km0c = (k0 > 0) ? km0 : cur.x;
