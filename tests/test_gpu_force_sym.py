@@ -133,3 +133,42 @@ def test_sym_large_blocks(n):
     del c
     tot = np.abs((ah * ms).sum(axis=1))
     assert np.all(tot <= 1e-6 * (np.abs(ah) * ms).sum())
+
+
+@pytest.mark.parametrize("n", (1000, 20000))
+def test_degenerate_coincident_and_massless(n):
+    """Coincident particles (d = 0 between distinct i, j: no force between
+    them, eps > 0 keeps s finite) and massless test particles (feel the
+    others, pull on nothing), through the one-sided kernel (n = 1000) and the
+    symmetric pass (n = 20000), force and gradient."""
+    x, v, m = plummer_sphere(n, 250)
+    x[:, 10:20] = x[:, 5:6]                   # eleven particles at one point
+    x[:, n - 7:] = x[:, n - 8:n - 7]          # eight at another, in the last block
+    m = m.copy()
+    m[::97] = 0.0                             # test particles
+    eps = 2.0 ** -7
+    xd, vd, md = to_dev(x, v, m, PREC)
+    a = host(nb.accel(xd, md, eps, prec=PREC))
+    assert np.all(np.isfinite(a))
+    ref = oracle.accel(host(xd), host(md), eps)
+    assert rel(a, ref) <= TOL
+    # a massless particle moved far away changes no other particle's force
+    x2 = x.copy()
+    x2[:, 0] = x2[:, 0] + 50.0 if m[0] == 0 else x2[:, 0]
+    a2 = host(nb.accel(to_dev(x2, v, m, PREC)[0], md, eps, prec=PREC))
+    assert rel(a2[:, 1:], a[:, 1:]) <= 1e-6
+    # gradient of a short rollout stays finite and matches the oracle
+    S = 2
+    y = x + 0.01
+    xg, vg, mg = to_dev(x, v, m, PREC)
+    for t in (xg, vg, mg):
+        t.requires_grad_(True)
+    xs, _ = nb.rollout(xg, vg, mg, eps, 2.0 ** -8, S, ckpt_every=1, prec=PREC)
+    ((xs - torch.tensor(y, device=DEV)) ** 2).sum().backward()
+    _, _, _, tx, _ = oracle.kdk(host(xd), host(vd), host(md), eps, 2.0 ** -8, S, trajectory=True)
+    xo = tx[-1]
+    go = oracle.adjoint(tx, host(md), eps, 2.0 ** -8, 2.0 * (xo - y), np.zeros_like(v))
+    for g, r in zip((xg.grad, vg.grad, mg.grad), go):
+        gh = host(g)
+        assert np.all(np.isfinite(gh))
+        assert rel(gh, r) <= 1e-4
