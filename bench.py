@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="scale-2^20")
     ap.add_argument("--rollout", type=int, default=10, help="KDK steps per forward+adjoint pass")
+    ap.add_argument("--ckpt-every", type=int, default=20,
+                    help="checkpoint interval of the rollout (1: every step, so that every "
+                         "adjoint pass reloads its state instead of walking it back)")
     ap.add_argument("--prec", default="mix_tilec")
     ap.add_argument("--cpu-sample", type=int, default=4096,
                     help="sinks in the CPU-oracle baseline sample (0: skip)")
@@ -212,7 +215,7 @@ def main():
     from paper_2411_18889_amd import _lib
 
     w = WORKLOADS[args.workload]
-    prec, R, K = args.prec, args.rollout, 20
+    prec, R, K = args.prec, args.rollout, max(1, args.ckpt_every)
     dev = torch.device("cuda:0")
     print("device:", nb.device_info(), flush=True)
     t0 = time.time()
