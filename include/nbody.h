@@ -20,9 +20,22 @@
  *   precision policy `prec` (nb_prec below). Every pointer must be aligned to
  *   its element size. All device pointers are HIP device (or managed)
  *   memory owned by the caller; the library never allocates, frees or
- *   retains memory. Scratch memory comes from the caller's workspace `ws`
- *   (device memory, 256-byte aligned, at least nbody_workspace_size() bytes;
- *   may be NULL when that size is 0).
+ *   retains device memory for data (the HIP graphs that nbody_step keeps for
+ *   NB_GRAPH are runtime objects, freed by nbody_graph_cache_clear()).
+ *   Scratch memory comes from the caller's workspace `ws` (device memory,
+ *   256-byte aligned, at least nbody_workspace_size() bytes; may be NULL
+ *   when that size is 0).
+ *
+ * Pair passes and reproducibility
+ *   The pair sums run in one of two forms, chosen by n and the policy
+ *   (nbody_pass_info reports which): a one-sided kernel (every sink sums all
+ *   sources; optional split of the source range with FP64 partials), or, for
+ *   NB_MIX_TILEC with one set acting on itself from 16384 particles, a
+ *   symmetric pass that evaluates each pair once for both bodies (Newton's
+ *   third law) and adds FP32 partials per particle block in block order. No
+ *   atomics in either: the same call on the same inputs gives bitwise the
+ *   same results. Results of different forms or launch shapes differ by
+ *   rounding only.
  *
  * Streams and synchronisation
  *   `stream` is a hipStream_t (NULL = the default stream). Every entry point
