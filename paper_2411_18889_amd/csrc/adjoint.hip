@@ -20,6 +20,8 @@
 // Tiling, j-split and the fixed-order split reduction are as in the force
 // kernel; the LDS record of a source is (x, y, z, m) and (lam_x, lam_y,
 // lam_z, 0).
+#include <algorithm>
+
 #include "common.h"
 
 namespace nb {
@@ -212,15 +214,20 @@ hipError_t launch_any(const Shape& sh, AdjArgs<Pol> a, int nsplit, hipStream_t s
 Shape choose_adjoint_shape(int prec, int64_t n) {
     // Measured on MI355X: one sink per lane (the fused pair body is long
     // enough to hide latency on its own; two sinks per lane run 13 % slower),
-    // 512-lane workgroups from 2^19 sinks up, and a source split up to ~128K
-    // wavefronts (8 ranges at 2^20, 32 at 2^14), every range >= 2 tiles long.
+    // 512-lane workgroups from 2^19 sinks up, 256 from 4096, 64 below; a
+    // source split up to ~128K wavefronts (8 ranges at 2^20), every range
+    // >= 2 tiles long (4 below 32768 sinks) -- or, below 16384 sinks, as
+    // short as one tile up to 32 ranges (2.2-2.8x faster at N = 1024 and
+    // 2048, where the pass is otherwise a handful of workgroups).
     (void)prec;
-    Shape s{1, n >= (1 << 19) ? 512 : 256, 1};
+    Shape s{1, n >= (1 << 19) ? 512 : (n <= 2048 ? 64 : 256), 1};
     const int64_t waves = (n + s.block - 1) / s.block * (s.block / 64);
     const int64_t want = 131072;
     int64_t split = (want + waves - 1) / waves;
-    const int64_t max_by_tiles = n / (2 * (int64_t)s.block);
-    if (split > max_by_tiles) split = max_by_tiles;
+    const int64_t long_ranges = n / ((n < 32768 ? 4 : 2) * (int64_t)s.block);
+    const int64_t short_ranges = n < 16384 ? std::min<int64_t>(32, n / (int64_t)s.block) : 0;
+    const int64_t max_ranges = std::max(long_ranges, short_ranges);
+    if (split > max_ranges) split = max_ranges;
     if (split > 256) split = 256;
     if (split < 1) split = 1;
     s.split = (int)split;
