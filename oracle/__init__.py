@@ -5,8 +5,8 @@ benchmark's CPU-baseline leg to check and time the GPU library, never by the
 GPU library itself. It shares no code with it.
 """
 
-from .oracle import (accel, accel_sampled, kdk, diag, vjp, jvp, adjoint, diffusion3d,
+from .oracle import (accel, accel_sampled, kdk, diag, vjp, vjp_sampled, jvp, adjoint, diffusion3d,
                      num_threads, set_num_threads, DIAG_FIELDS)
 
-__all__ = ["accel", "accel_sampled", "kdk", "diag", "vjp", "jvp", "adjoint", "diffusion3d",
+__all__ = ["accel", "accel_sampled", "kdk", "diag", "vjp", "vjp_sampled", "jvp", "adjoint", "diffusion3d",
            "num_threads", "set_num_threads", "DIAG_FIELDS"]

@@ -28,6 +28,7 @@
  *   oracle_vjp,    the transposed Jacobian of Eq. (1) with respect to the
  *   oracle_jvp     positions and the masses applied to a vector, and the
  *                  Jacobian applied to a vector. Not in the paper.
+ *                  oracle_vjp_sampled returns chosen rows of oracle_vjp.
  *   oracle_diffusion3d  one explicit step of the 3-D diffusion equation
  *                  (section "3D diffusion equation"), the paper's second demo.
  *   oracle_adjoint reverse-mode derivative of a KDK trajectory, one sub-step
@@ -233,34 +234,62 @@ static void add_T_times(const double d[3], double s32, double s52,
  *   d a_k / d m_k = 0.
  * T is symmetric, so the transposes drop out. gt may be NULL.
  */
+static void vjp_row(int64_t n, int64_t k, const double *x, const double *m,
+                    const double *lam, double eps2, double G, double jt[3], double *gt)
+{
+    const double rk[3] = {x[k], x[n + k], x[2 * n + k]};
+    const double lk[3] = {lam[k], lam[n + k], lam[2 * n + k]};
+    double off[3] = {0, 0, 0};  /* sum_{i != k} m_k T(r_k - r_i) lam_i */
+    double diag[3] = {0, 0, 0}; /* sum_{j != k} m_j T(r_j - r_k) lam_k */
+    double g = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        if (i == k)
+            continue;
+        const double li[3] = {lam[i], lam[n + i], lam[2 * n + i]};
+        const double d[3] = {rk[0] - x[i], rk[1] - x[n + i], rk[2] - x[2 * n + i]};
+        const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+        const double s32 = s * sqrt(s);
+        const double s52 = s32 * s;
+        add_T_times(d, s32, s52, m[k], li, off);  /* T(r_k - r_i) */
+        add_T_times(d, s32, s52, m[i], lk, diag); /* T(r_i - r_k) = T(r_k - r_i) */
+        g += (li[0] * d[0] + li[1] * d[1] + li[2] * d[2]) / s32;
+    }
+    jt[0] = G * (off[0] - diag[0]);
+    jt[1] = G * (off[1] - diag[1]);
+    jt[2] = G * (off[2] - diag[2]);
+    *gt = G * g;
+}
+
 void oracle_vjp(int64_t n, const double *x, const double *m, const double *lam,
                 double eps, double G, double *jt, double *gt)
 {
     const double eps2 = eps * eps;
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; k++) {
-        const double rk[3] = {x[k], x[n + k], x[2 * n + k]};
-        const double lk[3] = {lam[k], lam[n + k], lam[2 * n + k]};
-        double off[3] = {0, 0, 0};  /* sum_{i != k} m_k T(r_k - r_i) lam_i */
-        double diag[3] = {0, 0, 0}; /* sum_{j != k} m_j T(r_j - r_k) lam_k */
-        double g = 0.0;
-        for (int64_t i = 0; i < n; i++) {
-            if (i == k)
-                continue;
-            const double li[3] = {lam[i], lam[n + i], lam[2 * n + i]};
-            const double d[3] = {rk[0] - x[i], rk[1] - x[n + i], rk[2] - x[2 * n + i]};
-            const double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
-            const double s32 = s * sqrt(s);
-            const double s52 = s32 * s;
-            add_T_times(d, s32, s52, m[k], li, off);  /* T(r_k - r_i) */
-            add_T_times(d, s32, s52, m[i], lk, diag); /* T(r_i - r_k) = T(r_k - r_i) */
-            g += (li[0] * d[0] + li[1] * d[1] + li[2] * d[2]) / s32;
-        }
-        jt[k] = G * (off[0] - diag[0]);
-        jt[n + k] = G * (off[1] - diag[1]);
-        jt[2 * n + k] = G * (off[2] - diag[2]);
+        double r[3], g;
+        vjp_row(n, k, x, m, lam, eps2, G, r, &g);
+        jt[k] = r[0];
+        jt[n + k] = r[1];
+        jt[2 * n + k] = r[2];
         if (gt)
-            gt[k] = G * g;
+            gt[k] = g;
+    }
+}
+
+/* The rows idx[0 .. ns) of oracle_vjp: jt is 3 x ns (SoA), gt ns. */
+void oracle_vjp_sampled(int64_t n, int64_t ns, const int64_t *idx, const double *x,
+                        const double *m, const double *lam, double eps, double G,
+                        double *jt, double *gt)
+{
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < ns; q++) {
+        double r[3], g;
+        vjp_row(n, idx[q], x, m, lam, eps2, G, r, &g);
+        jt[q] = r[0];
+        jt[ns + q] = r[1];
+        jt[2 * ns + q] = r[2];
+        gt[q] = g;
     }
 }
 

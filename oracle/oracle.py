@@ -40,12 +40,13 @@ def _load():
     lib.oracle_kdk.argtypes = [i64, _D, _D, _D, dbl, dbl, dbl, i64, _D, _D, _D]
     lib.oracle_diag.argtypes = [i64, _D, _D, _D, dbl, dbl, _D]
     lib.oracle_vjp.argtypes = [i64, _D, _D, _D, dbl, dbl, _D, _D]
+    lib.oracle_vjp_sampled.argtypes = [i64, i64, _I64, _D, _D, _D, dbl, dbl, _D, _D]
     lib.oracle_jvp.argtypes = [i64, _D, _D, _D, dbl, dbl, _D]
     lib.oracle_adjoint.argtypes = [i64, i64, _D, _D, dbl, dbl, dbl, _D, _D, _D]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_num_threads.restype = None
-    for f in ("oracle_accel", "oracle_kdk", "oracle_diag", "oracle_vjp",
+    for f in ("oracle_accel", "oracle_kdk", "oracle_diag", "oracle_vjp", "oracle_vjp_sampled",
               "oracle_jvp", "oracle_adjoint"):
         getattr(lib, f).restype = None
     _lib = lib
@@ -146,6 +147,19 @@ def vjp(x, m, lam, eps, G=1.0):
     gt = np.empty(n)
     lib.oracle_vjp(n, _p(x), _p(_f64(m, (n,))), _p(_f64(lam)), float(eps), float(G),
                    _p(jt), _p(gt))
+    return jt, gt
+
+
+def vjp_sampled(x, m, lam, eps, idx, G=1.0):
+    """Rows ``idx`` of vjp: (J^T lam)[:, idx] (3, len(idx)) and (G^T lam)[idx]."""
+    lib = _load()
+    x = _f64(x)
+    n = x.shape[1]
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    jt = np.empty((3, idx.size))
+    gt = np.empty(idx.size)
+    lib.oracle_vjp_sampled(n, idx.size, idx.ctypes.data_as(_I64), _p(x), _p(_f64(m, (n,))),
+                           _p(_f64(lam)), float(eps), float(G), _p(jt), _p(gt))
     return jt, gt
 
 

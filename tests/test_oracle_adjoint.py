@@ -149,3 +149,13 @@ def test_adjoint_position_sum_invariant():
     np.testing.assert_allclose(gx.sum(axis=1), lx.sum(axis=1), rtol=0, atol=1e-12)
     np.testing.assert_allclose(gv.sum(axis=1), lv.sum(axis=1) + S * dt * lx.sum(axis=1),
                                rtol=0, atol=1e-12)
+
+
+def test_vjp_sampled_rows_are_vjp_rows():
+    # the sampled form evaluates the same rows with the same arithmetic
+    x, v, m = plummer_sphere(300, 41)
+    lam = np.random.default_rng(2).normal(size=(3, 300))
+    jt, gt = oracle.vjp(x, m, lam, 2.0 ** -5, G=1.5)
+    idx = np.array([299, 0, 17, 17, 150])
+    js, gs = oracle.vjp_sampled(x, m, lam, 2.0 ** -5, idx, G=1.5)
+    assert np.array_equal(js, jt[:, idx]) and np.array_equal(gs, gt[idx])

@@ -38,7 +38,7 @@ MUTANTS = {
     "diag_L_sign": ("l[1] += m[i] * (rz * vx - rx * vz);", "l[1] += m[i] * (rx * vz - rz * vx);"),
     "T_factor": ("out[1] += c * (w[1] / s32 - 3.0 * d[1] * dw / s52);",
                  "out[1] += c * (w[1] / s32 - 2.0 * d[1] * dw / s52);"),
-    "vjp_diag_sign": ("jt[n + k] = G * (off[1] - diag[1]);", "jt[n + k] = G * (off[1] + diag[1]);"),
+    "vjp_diag_sign": ("jt[1] = G * (off[1] - diag[1]);", "jt[1] = G * (off[1] + diag[1]);"),
     "vjp_mass_transposed": ("add_T_times(d, s32, s52, m[k], li, off);", "add_T_times(d, s32, s52, m[i], li, off);"),
     "vjp_mass_grad_sign": ("g += (li[0] * d[0] + li[1] * d[1] + li[2] * d[2]) / s32;",
                            "g -= (li[0] * d[0] + li[1] * d[1] + li[2] * d[2]) / s32;"),
