@@ -205,3 +205,46 @@ def test_adjoint_symmetric_checkpoint_interval_invariance():
     for r in res[1:]:
         for a, b in zip(r, res[0]):
             assert rel(a, b) <= 1e-7
+
+
+@pytest.mark.parametrize("walk", (False, True))
+def test_adjoint_pass_full_size_against_oracle_rows(walk):
+    """scale-2^20, in the launch configuration the benchmark times: one fused
+    adjoint pass against the oracle's transposed Jacobians on sampled rows.
+    walk = False: the entry pass (state from the caller, force sums skipped);
+    walk = True: one step walked back with a tiny dt, so the pass also
+    computes a(x) and steps the velocity (the force-summing kernel)."""
+    from nbody_inputs import make_state
+    from tests.gpu_util import sample_indices
+    x, v, m = make_state("scale-2^20")
+    n = x.shape[1]
+    eps, G = 2.0 ** -10, 1.0
+    xd, vd, md = to_dev(x, v, m, "mix_tilec")
+    assert nb.pass_info(2, n, "mix_tilec")["symmetric"] == 1
+    acc = nb.accel(xd, md, eps, prec="mix_tilec")
+    lam = torch.tensor(np.random.default_rng(11).normal(size=(3, n)), device=DEV)
+    lx = torch.zeros_like(lam)
+    lm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    if walk:
+        dt = 2.0 ** -24
+        h = 0.5 * dt
+        # the state the pass will see: the reverse drift's arithmetic, in FP64
+        vh = host(vd) - h * host(acc)
+        xw = host(xd) - dt * vh
+        nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 1, G=G, prec="mix_tilec")
+        c = h  # the last (and only) pass of a walk ending at step 0
+    else:
+        dt = 2.0 ** -11
+        xw = host(xd)
+        nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 0, G=G, prec="mix_tilec",
+                        entry_half=True)
+        c = 0.5 * dt
+    idx = sample_indices(xw, 256, 32, seed=12)
+    jt, gt = oracle.vjp_sampled(xw, host(md), host(lam), eps, idx, G=G)
+    ex = rel(host(lx)[:, idx] / c, jt)
+    em = rel(host(lm)[idx] / c, gt)
+    print("scale-2^20 adjoint pass (walk=%s): J^T lam rel err %.3g, G^T lam %.3g" % (walk, ex, em))
+    assert ex <= 1e-4 and em <= 1e-4
+    if walk:  # the pass also left a(x) of the walked-back state
+        ea = rel(host(acc)[:, idx], oracle.accel_sampled(xw, host(md), eps, idx))
+        assert ea <= 1e-5
