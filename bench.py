@@ -47,7 +47,7 @@ def parse():
                     help="checkpoint interval of the rollout (1: every step, so that every "
                          "adjoint pass reloads its state instead of walking it back)")
     ap.add_argument("--prec", default="mix_tilec")
-    ap.add_argument("--cpu-sample", type=int, default=4096,
+    ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="sinks in the CPU-oracle baseline sample (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this many MiB (to "
@@ -352,7 +352,7 @@ def main():
         rel_err = float(np.linalg.norm(a_gpu[:, idx] - ref) / np.linalg.norm(ref))
         # the same oracle on one thread, over the first eighth of the sinks
         k0 = oracle.num_threads()
-        idx1 = idx[: max(1, len(idx) // 8)]
+        idx1 = idx[: max(1, min(1024, len(idx) // 8))]
         oracle.set_num_threads(1)
         tc = time.time()
         oracle.accel_sampled(xh, mh, w.eps, idx1)
