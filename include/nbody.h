@@ -141,7 +141,9 @@ typedef struct nb_launch {
  *                     phi_i = -G sum_j m_j / sqrt(|r_j - r_i|^2 + eps^2),
  *                     with the j = i term removed when xi == xj (the paper's
  *                     CALCULATE_POTENTIAL branch sums it in; here it is
- *                     subtracted once per sink after the sum)
+ *                     subtracted once per sink after the sum). In the
+ *                     symmetric pass the potential of a pair comes from the
+ *                     same reciprocal square root as its forces
  *   ws, ws_bytes      workspace, nbody_workspace_size(NB_OP_ACCEL, max(ni,nj), prec)
  *   stream            hipStream_t
  * Returns NB_EINVAL for ni < 1, nj < 1, ni or nj > 2^30, bad eps or G, a
@@ -272,7 +274,9 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
 /*
  * nbody_pass_info -- the pair pass the library runs for n particles acting
  * on themselves (op NB_OP_STEP: the force of a leapfrog, and of
- * nbody_accel with xi == xj, no potential and no explicit shape; op
+ * nbody_accel with xi == xj and no explicit shape -- with a potential the
+ * same, except that the symmetric pass keeps four partials per particle, so
+ * its block may grow earlier as the 16 GiB bound binds; op
  * NB_OP_ADJOINT: the fused adjoint pass of nbody_step_adjoint). Host-side
  * only (no device needed). NB_EINVAL for another op, n outside 1..2^30 or a
  * NULL out; NB_EUNSUPPORTED for an unknown prec.

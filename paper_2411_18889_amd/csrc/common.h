@@ -162,18 +162,20 @@ hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi
                         hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0);
 
 // Symmetric (third-law) force pass of one set on itself, NB_MIX_TILEC only:
-// blocks of waves*64*ipl particles; waves == 0 means "not used".
+// blocks of waves*64*ipl particles; waves == 0 means "not used". pot: the
+// pass also computes the potential (four partial quantities instead of three).
 struct SymShape {
     int waves;  // wavefronts per workgroup
     int ipl;    // sinks per lane
 };
-SymShape choose_sym_shape(int prec, int64_t n);
-size_t sym_partials_bytes(const SymShape& s, int64_t n);
-// acc = a(x) (and with kick_v, v <- v + kick_h * acc); ws holds
-// sym_partials_bytes(sh, n) bytes.
+SymShape choose_sym_shape(int prec, int64_t n, bool pot = false);
+size_t sym_partials_bytes(const SymShape& s, int64_t n, bool pot = false);
+// acc = a(x) (and with kick_v, v <- v + kick_h * acc; with pot, the
+// potential with the j = i term removed); ws holds
+// sym_partials_bytes(sh, n, pot != nullptr) bytes.
 hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                             double eps, double G, void* acc, void* ws, hipStream_t stream,
-                            void* kick_v = nullptr, double kick_h = 0.0);
+                            void* kick_v = nullptr, double kick_h = 0.0, void* pot = nullptr);
 
 // Fused adjoint pair pass at x with adjoint lam_v: computes a(x), J^T lam_v,
 // G^T lam_v and applies the epilogue

@@ -28,7 +28,12 @@
 //    exactly one partial in each slot k = 0 .. nb-1 (k < P: j side of item
 //    (k, P); k = P: item (P, P); k > P: i side of item (P, k)), and a second
 //    kernel adds the nb slots in slot order in FP64, then applies G and the
-//    optional closing half-kick.
+//    optional closing half-kick;
+//  * with the potential, the same reciprocal square root also gives the
+//    fourth quantity: m_j / r on the i side and m_i / r on the j side (no
+//    sign change, the potential is symmetric). The diagonal items include
+//    the j = i term m_i / eps, which the finish kernel removes with the same
+//    FP32 product the pair loop formed.
 #include "common.h"
 
 namespace nb {
@@ -42,14 +47,17 @@ struct SymArgs {
     const float* m;
     int n, nb;
     float eps2;
-    float* part;  // [nb][3][n]
+    float* part;  // [nb][NQ][n], NQ = 3, or 4 with the potential
 };
 
 struct SymFinishArgs {
     const float* part;
+    const float* m;  // for the j = i potential term
     int n, nb;
+    float eps2;
     double G;
     double *ax, *ay, *az;
+    double* pot;           // or nullptr
     double *vx, *vy, *vz;  // or nullptr
     double h;
 };
@@ -70,14 +78,14 @@ __device__ __forceinline__ float from_next_lane(float v) {
 // rec[g][l + t]: the step is an immediate offset of the LDS read. The j-side
 // sums of the group travel with their source, one lane down per step, so
 // after 64 steps lane l holds the sum of source l, which it stores in the
-// wave's LDS row jq[c][g*64 + l].
-template <int K, bool JSIDE>
+// wave's LDS row jq[c][g*64 + l]. P adds the potential as a fourth quantity.
+template <int K, bool JSIDE, bool P>
 __device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, const float* xi,
                                          const float* yi, const float* zi, const float* mi,
-                                         SumTile (*s)[3], float eps2, int lane) {
+                                         SumTile (*s)[4], float eps2, int lane) {
     for (int g = 0; g < TJ / 64; ++g) {
         const float4* row = rec[g] + lane;
-        float cx = 0.f, cy = 0.f, cz = 0.f;
+        float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
 #pragma unroll 4
         for (int t = 0; t < 64; ++t) {
             const float4 q = row[t];
@@ -93,40 +101,46 @@ __device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, co
                 s[k][0].add_fma(dx, wj);
                 s[k][1].add_fma(dy, wj);
                 s[k][2].add_fma(dz, wj);
+                if (P) s[k][3].add_fma(q.w, r);
                 if (JSIDE) {
                     const float wi = r3 * mi[k];
                     cx = fmat(dx, wi, cx);
                     cy = fmat(dy, wi, cy);
                     cz = fmat(dz, wi, cz);
+                    if (P) cp = fmat(mi[k], r, cp);
                 }
             }
             if (JSIDE) {
                 cx = from_next_lane(cx);
                 cy = from_next_lane(cy);
                 cz = from_next_lane(cz);
+                if (P) cp = from_next_lane(cp);
             }
         }
         if (JSIDE) {
             jq[g * 64 + lane] = cx;
             jq[TJ + g * 64 + lane] = cy;
             jq[2 * TJ + g * 64 + lane] = cz;
+            if (P) jq[3 * TJ + g * 64 + lane] = cp;
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             s[k][0].tile_end();
             s[k][1].tile_end();
             s[k][2].tile_end();
+            if (P) s[k][3].tile_end();
         }
     }
 }
 
-template <int W, int K>
+template <int W, int K, bool P>
 __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
     constexpr int NT = W * 64;
     constexpr int BI = NT * K;
+    constexpr int NQ = P ? 4 : 3;
     static_assert(BI % TJ == 0, "a block must hold whole tiles");
     __shared__ float4 rec[TJ / 64][128];
-    __shared__ float jacc[W][3][TJ];
+    __shared__ float jacc[W][NQ][TJ];
 
     // item -> (I, J), I <= J, items ordered by J then I
     const int64_t item = blockIdx.x;
@@ -141,7 +155,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
     const int w = tid >> 6;
     const int ibase = I * BI + w * 64 * K + lane;
     float xi[K], yi[K], zi[K], mi[K];
-    SumTile s[K][3];
+    SumTile s[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
@@ -153,6 +167,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
         s[k][0].init();
         s[k][1].init();
         s[k][2].init();
+        s[k][3].init();
     }
 
     const int jb = J * BI;
@@ -167,20 +182,21 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
         }
         __syncthreads();
         if (jside)
-            sym_tile<K, true>(rec, &jacc[w][0][0], xi, yi, zi, mi, s, a.eps2, lane);
+            sym_tile<K, true, P>(rec, &jacc[w][0][0], xi, yi, zi, mi, s, a.eps2, lane);
         else
-            sym_tile<K, false>(rec, nullptr, xi, yi, zi, mi, s, a.eps2, lane);
+            sym_tile<K, false, P>(rec, nullptr, xi, yi, zi, mi, s, a.eps2, lane);
         __syncthreads();
         if (jside) {
             // j side of this tile: the wave rows added in wave order (every
             // row entry is rewritten by the next tile before it is read again)
-            for (int q = tid; q < 3 * TJ; q += NT) {
+            // (the force on j is minus the sum, its potential the sum)
+            for (int q = tid; q < NQ * TJ; q += NT) {
                 const int c = q / TJ, jj = q - c * TJ;
                 float sum = 0.f;
 #pragma unroll
                 for (int v = 0; v < W; ++v) sum += jacc[v][c][jj];
                 const int j = jt + jj;
-                if (j < je) a.part[((size_t)I * 3 + c) * a.n + j] = -sum;
+                if (j < je) a.part[((size_t)I * NQ + c) * a.n + j] = c < 3 ? -sum : sum;
             }
         }
         // rec is rewritten only after every wave has passed the barrier above
@@ -190,21 +206,31 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
         const int i = ibase + k * 64;
         if (i >= a.n) continue;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.part[((size_t)J * 3 + c) * a.n + i] = float(s[k][c].total());
+        for (int c = 0; c < NQ; ++c) a.part[((size_t)J * NQ + c) * a.n + i] = float(s[k][c].total());
     }
 }
 
 // Adds the nb partials of every particle in slot order (FP64), then stores
-// a = G * sum and applies the optional half-kick v <- v + h a, with a as stored.
+// a = G * sum and applies the optional half-kick v <- v + h a, with a as
+// stored; with P, also the potential -G (sum - m_i / eps).
+template <bool P>
 __global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs a) {
+    constexpr int NQ = P ? 4 : 3;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
     for (int k = 0; k < a.nb; ++k) {
-        const float* p = a.part + (size_t)k * 3 * a.n;
+        const float* p = a.part + (size_t)k * NQ * a.n;
         sx += double(p[i]);
         sy += double(p[(size_t)a.n + i]);
         sz += double(p[(size_t)2 * a.n + i]);
+        if (P) sp += double(p[(size_t)3 * a.n + i]);
+    }
+    if (P) {
+        // the j = i term as the pair loop formed it: m_i times the FP32
+        // reciprocal square root of eps^2, one FP32 product
+        const double self = double(a.m[i] * rsqrt_pair(a.eps2));
+        a.pot[i] = -a.G * (sp - self);
     }
     const double ax = a.G * sx, ay = a.G * sy, az = a.G * sz;
     a.ax[i] = ax;
@@ -218,9 +244,14 @@ __global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs a) 
 }
 
 template <int W, int K>
-hipError_t launch_sym(const SymArgs& a, hipStream_t stream) {
+hipError_t launch_sym(const SymArgs& a, bool pot, hipStream_t stream) {
     const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
-    hipLaunchKernelGGL((force_sym_kernel<W, K>), dim3((unsigned)items), dim3(W * 64), 0, stream, a);
+    if (pot)
+        hipLaunchKernelGGL((force_sym_kernel<W, K, true>), dim3((unsigned)items), dim3(W * 64), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((force_sym_kernel<W, K, false>), dim3((unsigned)items), dim3(W * 64), 0,
+                           stream, a);
     return hipGetLastError();
 }
 
@@ -228,12 +259,13 @@ constexpr size_t kSymWorkspaceCap = size_t(16) << 30;
 
 }  // namespace
 
-SymShape choose_sym_shape(int prec, int64_t n) {
+SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // Measured on MI355X at N = 2^18 and 2^20: four-wave workgroups with four
     // sinks per lane (blocks of 1024) are fastest -- more waves per SIMD than
     // the larger workgroups, and one source rotation per four pairs. Blocks
     // are kept to at most n/48 (>= 1176 equal work items for the 256 CUs),
-    // and grown only when the FP32 partials (nb * 3 * n floats) would pass
+    // and grown only when the FP32 partials (nb * 3 * n floats, or
+    // nb * 4 * n with the potential) would pass
     // the workspace cap; past the largest block the one-sided kernel is used.
     // Below 16384 particles the one-sided kernel is as fast (measured: 6 %
     // slower at 12288, 10 % faster at 16384, 37 % at 24576).
@@ -243,20 +275,20 @@ SymShape choose_sym_shape(int prec, int64_t n) {
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48) ++k;
-    while (k < NC && sym_partials_bytes(cands[k], n) > kSymWorkspaceCap) ++k;
+    while (k < NC && sym_partials_bytes(cands[k], n, pot) > kSymWorkspaceCap) ++k;
     return k < NC ? cands[k] : SymShape{0, 0};
 }
 
-size_t sym_partials_bytes(const SymShape& s, int64_t n) {
+size_t sym_partials_bytes(const SymShape& s, int64_t n, bool pot) {
     if (s.waves == 0) return 0;
     const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
     const int64_t nb = (n + bi - 1) / bi;
-    return (size_t)nb * 3 * (size_t)n * sizeof(float);
+    return (size_t)nb * (pot ? 4 : 3) * (size_t)n * sizeof(float);
 }
 
 hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                             double eps, double G, void* acc, void* ws, hipStream_t stream,
-                            void* kick_v, double kick_h) {
+                            void* kick_v, double kick_h, void* pot) {
     const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
     if (bi == 0) return hipErrorInvalidValue;
     SymArgs a{};
@@ -271,15 +303,18 @@ hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const 
     a.part = static_cast<float*>(ws);
     hipError_t e = hipErrorInvalidValue;
 #define NB_SYM_CASE(WV, KV) \
-    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<WV, KV>(a, stream);
+    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<WV, KV>(a, pot != nullptr, stream);
     NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
 #undef NB_SYM_CASE
     if (e != hipSuccess) return e;
     SymFinishArgs f{};
     f.part = a.part;
+    f.m = a.m;
     f.n = a.n;
     f.nb = a.nb;
+    f.eps2 = a.eps2;
     f.G = G;
+    f.pot = static_cast<double*>(pot);
     double* po = static_cast<double*>(acc);
     f.ax = po;
     f.ay = po + n;
@@ -291,8 +326,11 @@ hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const 
         f.vz = pv + 2 * n;
         f.h = kick_h;
     }
-    hipLaunchKernelGGL(force_sym_finish_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                       stream, f);
+    const dim3 fg((unsigned)((n + 255) / 256));
+    if (pot)
+        hipLaunchKernelGGL(force_sym_finish_kernel<true>, fg, dim3(256), 0, stream, f);
+    else
+        hipLaunchKernelGGL(force_sym_finish_kernel<false>, fg, dim3(256), 0, stream, f);
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <vector>
@@ -220,9 +221,10 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
                 overlaps(pot, (size_t)ni * ps, xi, 3 * (size_t)ni * ps) ||
                 overlaps(pot, (size_t)ni * ps, xj, 3 * (size_t)nj * ps)))
         return NB_EINVAL;
-    // one set on itself, no potential, library shape: the symmetric pass
-    // where the policy has one
-    const SymShape sym = (self_set && !pot && !launch) ? choose_sym_shape(prec, ni) : SymShape{0, 0};
+    // one set on itself, library shape: the symmetric pass where the policy
+    // has one
+    const SymShape sym =
+        (self_set && !launch) ? choose_sym_shape(prec, ni, pot != nullptr) : SymShape{0, 0};
     Shape sh = choose_force_shape(prec, ni, nj);
     if (launch) {
         if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
@@ -230,12 +232,13 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
         if (launch->split) sh.split = launch->split;
         if (!shape_supported(sh)) return NB_EUNSUPPORTED;
     }
-    int st = check_ws(ws, ws_bytes, sym.waves ? sym_partials_bytes(sym, ni) : accel_ws(sh, ni));
+    int st = check_ws(ws, ws_bytes,
+                      sym.waves ? sym_partials_bytes(sym, ni, pot != nullptr) : accel_ws(sh, ni));
     if (st != NB_OK) return st;
     if ((st = check_device()) != NB_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return hip_status(timed(NB_PROF_FORCE, s, [&] {
-        if (sym.waves) return launch_force_sym(sym, ni, xi, mj, eps, G, acc, ws, s);
+        if (sym.waves) return launch_force_sym(sym, ni, xi, mj, eps, G, acc, ws, s, nullptr, 0.0, pot);
         return launch_force(prec, sh, ni, xi, nj, xj, mj, eps, G, self_set, acc, pot, ws, s);
     }));
 }
@@ -469,10 +472,11 @@ int diffusion3d_step(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, d
 size_t nbody_workspace_size(int op, int64_t n, int prec) {
     if (!valid_prec(prec) || n < 1 || n > kMaxN) return 0;
     switch (op) {
-    case NB_OP_ACCEL: {  // either pass may run
+    case NB_OP_ACCEL: {  // either pass may run, with or without the potential
         const size_t a = accel_ws(choose_force_shape(prec, n, n), n);
         const size_t b = sym_partials_bytes(choose_sym_shape(prec, n), n);
-        return a > b ? a : b;
+        const size_t c = sym_partials_bytes(choose_sym_shape(prec, n, true), n, true);
+        return std::max(a, std::max(b, c));
     }
     case NB_OP_STEP: {
         const SymShape sym = choose_sym_shape(prec, n);

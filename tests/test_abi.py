@@ -67,6 +67,13 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(1, 1 << 21, TILEC) == 512 * 3 * (1 << 21) * 4
     assert L.nbody_workspace_size(1, 3 << 20, TILEC) < 1 << 30  # one-sided kernel
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
+    # nbody_accel covers the symmetric pass with the potential too: four
+    # partials per particle and block, the block grown by the same bound
+    assert L.nbody_workspace_size(0, 16384, TILEC) == 64 * 4 * 16384 * 4
+    assert L.nbody_workspace_size(0, 1 << 20, TILEC) == 1024 * 4 * (1 << 20) * 4
+    # (at 1,200,000 the potential pass takes blocks of 2048, 586 x 4 partials,
+    # and the pass without it still 1172 x 3)
+    assert L.nbody_workspace_size(0, 1_200_000, TILEC) == 1172 * 3 * 1_200_000 * 4
     # and the symmetric adjoint pass: seven FP32 partials per particle and
     # block (blocks of min(n/64, 512), larger while past 16 GiB, up to 2048)
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4

@@ -135,6 +135,43 @@ def test_sym_large_blocks(n):
     assert np.all(tot <= 1e-6 * (np.abs(ah) * ms).sum())
 
 
+@pytest.mark.parametrize("n", (16384, 24576 + 7, 65536 + 1000, 1_200_000))
+def test_sym_potential(n):
+    """The potential from the symmetric pass (a fourth partial per particle
+    and block, the j = i term removed after the sum): against the oracle
+    (every sink up to 40000, sampled above) and the one-sided kernel on every
+    sink. Its accelerations are those of the pass without the potential --
+    bitwise where both use the same blocks; at 1,200,000 the four partials
+    pass the 16 GiB bound and the potential pass takes blocks of 2048."""
+    x, v, m = plummer_sphere(n, 260 + n % 89)
+    m = m * np.random.default_rng(n + 1).uniform(0.5, 1.5, size=n)  # unequal masses
+    eps = 2.0 ** -9
+    xd, _, md = to_dev(x, v, m, PREC)
+    a, pot = nb.accel(xd, md, eps, prec=PREC, potential=True)
+    a0 = nb.accel(xd, md, eps, prec=PREC)
+    if n < 1_000_000:
+        assert torch.equal(a, a0)
+    else:
+        assert float((a - a0).norm() / a0.norm()) <= 1e-6
+    del a0
+    ph = host(pot)
+    xs, ms = host(xd), host(md)
+    if n <= 40000:
+        ra, rp = oracle.accel(xs, ms, eps, potential=True)
+        ea, ep = rel(host(a), ra), rel(ph, rp)
+    else:
+        idx = sample_indices(xs, 256 if n > 500000 else 1024, 32, seed=n)
+        ra, rp = oracle.accel_sampled(xs, ms, eps, idx, potential=True)
+        ea, ep = rel(host(a)[:, idx], ra), rel(ph[idx], rp)
+    print("n=%d sym potential e_glob %.3g (acc %.3g)" % (n, ep, ea))
+    assert ea <= TOL and ep <= TOL
+    c, cp = nb.accel(xd, md, eps, prec=PREC, potential=True,
+                     launch={"i_per_lane": 2, "block": 256, "split": 1})
+    assert float((pot - cp).norm() / cp.norm()) <= TOL
+    assert float((pot - cp).abs().max() / cp.abs().max()) <= 1e-5
+    assert bool((pot < 0).all())
+
+
 @pytest.mark.parametrize("n", (1000, 20000))
 def test_degenerate_coincident_and_massless(n):
     """Coincident particles (d = 0 between distinct i, j: no force between
