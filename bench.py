@@ -32,6 +32,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12      # MI355X published FP32 vector peak (counts packed FP32)
+PEAK_CLOCK_MHZ = 2400.0          # the shader clock the published peaks assume
 FLOP_PER_FORCE_PAIR = 20         # 3 sub + 3 FMA + 3 mul + 3 FMA (FMA = 2) + 2 for rsqrt
 FLOP_PER_ADJOINT_PAIR = 55       # count of the fused adjoint pair body, same convention
 
@@ -86,6 +87,41 @@ def gpu_clocks():
         if out:
             break
     return out
+
+
+class ClockSampler:
+    """Samples the shader clock (sysfs pp_dpm_sclk, current level) every
+    `period` seconds on a host thread while the timed steps run; the peak
+    figures assume 2.4 GHz, and the clock under a sustained load sits below
+    it when the power cap binds."""
+
+    def __init__(self, period=0.1):
+        import threading
+        self.period, self.samples = period, []
+        self._stop = threading.Event()
+        self._t = threading.Thread(target=self._run, daemon=True)
+
+    def _run(self):
+        while not self._stop.is_set():
+            c = gpu_clocks().get("sclk_mhz")
+            if c:
+                self.samples.append(c)
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        self._t.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        self._t.join()
+
+    def summary(self):
+        if not self.samples:
+            return {}
+        v = self.samples
+        return {"sclk_mhz_mean": sum(v) / len(v), "sclk_mhz_min": min(v), "sclk_mhz_max": max(v),
+                "samples": len(v), "source": "sysfs pp_dpm_sclk, every %.1f s" % self.period}
 
 
 def kernel_source_hash(kernel):
@@ -275,13 +311,14 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     _lib.check(L.nbody_profile_begin(), "nbody_profile_begin")
-    ev0.record(stream)
-    wall0 = time.time()
-    for i in range(args.steps):
-        one_step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.time() - wall0
+    with ClockSampler() as clocks:
+        ev0.record(stream)
+        wall0 = time.time()
+        for i in range(args.steps):
+            one_step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.time() - wall0
     _lib.check(L.nbody_profile_end(ctypes.byref(prof)), "nbody_profile_end")
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
@@ -330,6 +367,12 @@ def main():
                   "pair_evaluations_per_interaction": pairs_per_interaction,
                   "shape": fpass,
                   "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
+
+    clk = clocks.summary()
+    if clk:
+        # the same achieved rate against the peak scaled to the measured clock
+        for r in (roof, force_roof):
+            r["frac_at_measured_sclk"] = r["frac"] * PEAK_CLOCK_MHZ / clk["sclk_mhz_mean"]
 
     D0 = nb.diag_dict(d0)
     D1 = nb.diag_dict(d1)
@@ -394,6 +437,7 @@ def main():
         "adjoint_over_forward_kernel": a_ms / f_ms,
         "force_rel_err_sampled": rel_err,
         "energy_drift": dE,
+        "gpu_clocks_timed_region": clk,
         "gpu_clocks_after_run": gpu_clocks(),
         "per_kind": per_kind,
         "cpu_baseline": cpu,
