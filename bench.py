@@ -423,7 +423,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair arithmetic, f64 sums/state" if prec.startswith("mix") else prec,
+        "dtype": "f32" if prec.startswith("mix") else prec,
+        "precision": ("f32 pair arithmetic, f64 sums and state" if prec.startswith("mix")
+                      else prec + " throughout"),
         "data": "synthetic: seeded Plummer sphere",
         "config": {"workload": w.name, "n": n, "eps": w.eps, "dt": w.dt, "rollout_steps": R,
                    "ckpt_every": K, "precision": prec,
