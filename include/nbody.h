@@ -268,7 +268,10 @@ int nbody_profile_begin(void);
 int nbody_profile_end(nb_profile *out);
 
 /* Workspace bytes an operation needs for n particles (0 = none). For
- * NB_OP_ACCEL pass max(ni, nj). Returns 0 for an invalid op or prec. */
+ * NB_OP_ACCEL pass max(ni, nj): the size covers every call whose ni and nj
+ * are both <= n (a small sink set against many sources takes the most
+ * source ranges: up to 512 MiB of partials from n = 2^19 on). Returns 0 for
+ * an invalid op or prec. */
 size_t nbody_workspace_size(int op, int64_t n, int prec);
 
 /*

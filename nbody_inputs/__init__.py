@@ -7,10 +7,11 @@ the HIP path (``paper_2411_18889_amd``) can consume its output without sharing
 any of the method's arithmetic.
 """
 
-from .plummer import plummer_sphere, plummer_with_subcluster
+from .plummer import plummer_positions_device, plummer_sphere, plummer_with_subcluster
 from .configs import WORKLOADS, Workload, make_state, perturb_state, random_unit_vectors
 
 __all__ = [
+    "plummer_positions_device",
     "plummer_sphere",
     "plummer_with_subcluster",
     "WORKLOADS",

@@ -121,3 +121,35 @@ def plummer_with_subcluster(n_total: int, seed_main: int, seed_sub: int,
     m = np.full(n_total, mp)
     x, v = _to_com_frame(x, v, m)
     return x, v, m
+
+
+def plummer_positions_device(n: int, seed: int, device, a: float = 1.0, rmax: float = 10.0,
+                             chunk: int = 1 << 26):
+    """Positions only, (3, n) float64 torch tensor on `device`, drawn there
+    from a seeded ``torch.Generator`` with the same recipe as
+    ``plummer_sphere`` (radius by inverting the mass profile, truncated at
+    rmax by redrawing; isotropic direction), in chunks so that sizes up to
+    2^30 need no host memory. Not bitwise equal to ``plummer_sphere`` (a
+    different generator), and not shifted to the centre-of-mass frame."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty((3, n), dtype=torch.float64, device=device)
+    for k0 in range(0, n, chunk):
+        k = min(chunk, n - k0)
+        r = torch.empty(k, dtype=torch.float64, device=device)
+        todo = torch.arange(k, device=device)
+        while todo.numel():
+            X = torch.rand(todo.numel(), dtype=torch.float64, device=device, generator=g)
+            rr = a / torch.sqrt(X ** (-2.0 / 3.0) - 1.0)
+            ok = torch.isfinite(rr) & (rr <= rmax)
+            r[todo[ok]] = rr[ok]
+            todo = todo[~ok]
+        cos_t = 2.0 * torch.rand(k, dtype=torch.float64, device=device, generator=g) - 1.0
+        phi = 2.0 * torch.pi * torch.rand(k, dtype=torch.float64, device=device, generator=g)
+        sin_t = torch.sqrt(torch.clamp(1.0 - cos_t * cos_t, min=0.0))
+        out[0, k0:k0 + k] = r * sin_t * torch.cos(phi)
+        out[1, k0:k0 + k] = r * sin_t * torch.sin(phi)
+        out[2, k0:k0 + k] = r * cos_t
+    return out

@@ -151,6 +151,8 @@ bool shape_supported(const Shape& s);
 
 // Workspace bytes of the split partials of a force / adjoint launch.
 size_t force_partials_bytes(const Shape& s, int64_t ni);
+// Bound of the one-sided force partials over all ni, nj <= n.
+size_t force_partials_bound(int64_t n);
 size_t adjoint_partials_bytes(const Shape& s, int64_t n);
 
 // Force: acc (and pot) of ni sinks. self_set: xi and xj are the same set.

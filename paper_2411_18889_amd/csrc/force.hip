@@ -256,6 +256,25 @@ size_t force_partials_bytes(const Shape& s, int64_t ni) {
     return (size_t)s.split * NQ * (size_t)ni * sizeof(double);
 }
 
+// Upper bound of force_partials_bytes(choose_force_shape(prec, ni, nj), ni)
+// over every ni, nj <= n (a small sink set against a large source set takes
+// the most ranges). From the rule below:
+//  * a range is at least 4 tiles of >= 128 sources, or 8 of 64, i.e. >= 512
+//    sources, except that below 16384 sources ranges as short as one tile
+//    are allowed, at most 64 of them: split <= max(n/512, min(64, nj/64));
+//  * split <= 256;
+//  * split > 1 only while waves < 65536, where split <= 65536/waves + 1 and
+//    ni <= waves * 64 * ipl, so split * ni < 2^23 * ipl <= 2^24 for the
+//    shapes with ipl <= 2; the shape with ipl = 4 serves fewer than 65536
+//    sinks, so there split * ni <= 256 * 65536 = 2^24 as well.
+size_t force_partials_bound(int64_t n) {
+    const int64_t short_ranges = std::min<int64_t>(64, std::min<int64_t>(n, 16383) / 64);
+    const int64_t split = std::min<int64_t>(256, std::max<int64_t>(n / 512, short_ranges));
+    if (split <= 1) return 0;
+    const int64_t rows = std::min<int64_t>(split * n, int64_t(1) << 24);  // split * ni
+    return (size_t)rows * NQ * sizeof(double);
+}
+
 Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
     // Measured on MI355X (launch-shape sweeps at N = 2^10 .. 2^20):
     //  * FP32 pair arithmetic: 1 sink per lane in 256-lane workgroups up to

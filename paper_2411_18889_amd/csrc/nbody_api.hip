@@ -472,8 +472,8 @@ int diffusion3d_step(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, d
 size_t nbody_workspace_size(int op, int64_t n, int prec) {
     if (!valid_prec(prec) || n < 1 || n > kMaxN) return 0;
     switch (op) {
-    case NB_OP_ACCEL: {  // either pass may run, with or without the potential
-        const size_t a = accel_ws(choose_force_shape(prec, n, n), n);
+    case NB_OP_ACCEL: {  // any ni, nj <= n; either pass, with or without the potential
+        const size_t a = std::max(accel_ws(choose_force_shape(prec, n, n), n), force_partials_bound(n));
         const size_t b = sym_partials_bytes(choose_sym_shape(prec, n), n);
         const size_t c = sym_partials_bytes(choose_sym_shape(prec, n, true), n, true);
         return std::max(a, std::max(b, c));

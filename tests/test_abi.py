@@ -69,8 +69,13 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
     # nbody_accel covers the symmetric pass with the potential too: four
     # partials per particle and block, the block grown by the same bound
-    assert L.nbody_workspace_size(0, 16384, TILEC) == 64 * 4 * 16384 * 4
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) == 1024 * 4 * (1 << 20) * 4
+    # and a small sink set against up to n sources: at most 64 one-tile source
+    # ranges below 16384 sources, n / 512 above, <= 2^24 sink-ranges in all,
+    # 4 FP64 partials each
+    assert L.nbody_workspace_size(0, 16384, TILEC) == 64 * 16384 * 4 * 8
+    assert L.nbody_workspace_size(0, 1 << 30, TILEC) == (1 << 24) * 4 * 8
+    assert L.nbody_workspace_size(0, 1 << 30, F64) == (1 << 24) * 4 * 8
     # (at 1,200,000 the potential pass takes blocks of 2048, 586 x 4 partials,
     # and the pass without it still 1172 x 3)
     assert L.nbody_workspace_size(0, 1_200_000, TILEC) == 1172 * 3 * 1_200_000 * 4
@@ -81,6 +86,31 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
     assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 512 * 7 * (1 << 20) * 4
     assert L.nbody_workspace_size(2, 1 << 21, TILEC) < 1 << 30  # one-sided kernel
+
+
+def test_accel_workspace_covers_every_set_size(L):
+    """nbody_workspace_size(NB_OP_ACCEL, max(ni, nj)) is enough for every
+    ni, nj up to it. Checked through the library's own validation, which
+    rejects a short workspace (NB_EWORKSPACE) before it looks for a device,
+    so without a GPU every sufficient call ends at NB_ENODEV."""
+    base = 1 << 40
+    xi, xj, mj, acc, pot, ws = (base + (k << 38) for k in range(6))
+    sinks = {1, 16, 63, 64, 65, 255, 256, 257, 1000, 3071, 3072, 4095, 12288, 12289, 16383,
+             16384, 65535, 65536, 65537, 1 << 20}
+    sinks |= {g * 1024 for g in range(4096, 8193, 257)} | {8191 * 1024, 4097 * 1024 - 1}
+    for prec in range(6):
+        for nmax in (100, 1000, 5000, 20000, 70000, 1 << 20, 1 << 22, 1 << 24, 1 << 30):
+            w = L.nbody_workspace_size(0, nmax, prec)
+            for ni in sorted(k for k in sinks if k <= nmax) + [nmax]:
+                for nj in {nmax, max(1, nmax // 3)}:
+                    if max(ni, nj) != nmax:
+                        continue
+                    srcs = (xj, xi) if ni == nj else (xj,)  # and the set on itself
+                    for src in srcs:
+                        for p in (None, pot):
+                            st = L.nbody_accel(ni, xi, nj, src, mj, 0.01, 1.0, prec, acc, p,
+                                               ws if w else None, w, None)
+                            assert st == NB_ENODEV, (prec, nmax, ni, nj, src == xi, p, st)
 
 
 def _accel(L, ni=64, xi=A, nj=64, xj=B, mj=C, eps=0.1, G=1.0, prec=F64, acc=D, pot=None,
@@ -109,13 +139,20 @@ def test_accel_validation(L):
 
 
 def test_accel_workspace_checked_before_device(L):
-    need = L.nbody_workspace_size(0, 4096, TILEC)
-    assert need > 0
+    bound = L.nbody_workspace_size(0, 4096, TILEC)
     args = dict(ni=4096, nj=4096, xi=P(0x1000000), xj=P(0x2000000), mj=P(0x3000000),
                 acc=P(0x4000000), prec=TILEC)
     assert _accel(L, **args) == NB_EWORKSPACE
-    assert _accel(L, ws=P(0x5000000), wsb=need - 1, **args) == NB_EWORKSPACE
-    assert _accel(L, ws=P(0x5000000 + 128), wsb=need, **args) == NB_EWORKSPACE  # not 256-aligned
+    assert _accel(L, ws=P(0x5000000), wsb=bound, **args) == NB_ENODEV
+    # the exact need of this call, found through the validation itself:
+    # 16 source ranges x 4 FP64 partials per sink
+    lo, hi = 0, bound
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        lo, hi = (lo, mid) if _accel(L, ws=P(0x5000000), wsb=mid, **args) == NB_ENODEV else (mid, hi)
+    assert hi == 16 * 4 * 4096 * 8 <= bound
+    assert _accel(L, ws=P(0x5000000), wsb=hi - 1, **args) == NB_EWORKSPACE
+    assert _accel(L, ws=P(0x5000000 + 128), wsb=hi, **args) == NB_EWORKSPACE  # not 256-aligned
 
 
 def test_accel_ex_rejects_bad_shapes(L):

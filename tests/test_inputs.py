@@ -79,3 +79,24 @@ def test_subcluster_split():
 def test_make_state_override_n():
     x, _, m = make_state("adjoint-16384", n=256)
     assert x.shape == (3, 256) and np.all(m == 1 / 256)
+
+
+def test_device_positions_profile_and_determinism():
+    """The chunked torch generator used for the largest sizes: same seed
+    and chunk, same array; the truncated Plummer mass profile (KS test) and
+    isotropy (mean direction near 0)."""
+    scipy_stats = pytest.importorskip("scipy.stats")
+    torch = pytest.importorskip("torch")
+    from nbody_inputs import plummer_positions_device
+    n = 100000
+    x = plummer_positions_device(n, 11, "cpu", chunk=30000)
+    assert x.shape == (3, n) and x.dtype == torch.float64
+    assert torch.equal(x, plummer_positions_device(n, 11, "cpu", chunk=30000))
+    assert not torch.equal(x, plummer_positions_device(n, 12, "cpu", chunk=30000))
+    r = torch.linalg.norm(x, dim=0).numpy()
+    assert r.max() <= 10.0
+    norm = 1000.0 / 101.0 ** 1.5
+    ks = scipy_stats.kstest(r, lambda q: q ** 3 / (1 + q * q) ** 1.5 / norm)
+    assert ks.pvalue > 1e-3, ks
+    u = (x / torch.linalg.norm(x, dim=0)).mean(dim=1).abs().max().item()
+    assert u < 5.0 / np.sqrt(n)
