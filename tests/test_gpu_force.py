@@ -133,3 +133,55 @@ def test_acc32_subcluster_reported():
     e = rel(a[:, idx], oracle.accel_sampled(xs, ms, 2.0 ** -9, idx))
     print("subcluster-262144 mix_acc32: e_glob %.3g" % e)
     assert e <= 1e-4
+
+
+MAX_N = 1 << 30  # the largest particle count the library accepts
+
+
+@pytest.mark.parametrize("prec", ["mix_tilec", "f64"])
+def test_max_size_sink_set(prec):
+    """2^30 sinks, the largest count the ABI accepts, against 1000 sources
+    (several tiles and a ragged tail), with the potential: the sink indexing
+    at the top of its range. Sampled sinks, the first and the last ones
+    among them, against the oracle. Positions are seeded Plummer draws made
+    on the device (2^30 of them would take minutes on the host)."""
+    from nbody_inputs import plummer_positions_device
+    pdt, mdt = nb.pos_dtype(prec), nb.mass_dtype(prec)
+    xi = plummer_positions_device(MAX_N, 401, DEV).to(pdt)
+    xj = plummer_positions_device(1000, 402, DEV).to(pdt)
+    mj = torch.full((1000,), 1.0 / 1000, dtype=mdt, device=DEV)
+    eps = 2.0 ** -10
+    a, pot = nb.accel(xi, mj, eps, prec=prec, xj=xj, potential=True)
+    rng = np.random.default_rng(403)
+    idx = np.unique(np.concatenate([np.arange(64), rng.integers(0, MAX_N, 2048),
+                                    np.arange(MAX_N - 300, MAX_N)]))
+    it = torch.tensor(idx, device=DEV)
+    ah, ph, xs = host(a[:, it]), host(pot[it]), host(xi[:, it])
+    del a, pot, xi
+    torch.cuda.empty_cache()
+    ref, rpot = oracle.accel(xs, host(mj), eps, xj=host(xj), potential=True)
+    e, ep = rel(ah, ref), rel(ph, rpot)
+    print("%s: 2^30 sinks x 1000 sources, sampled e_glob %.3g, potential %.3g" % (prec, e, ep))
+    assert e <= TOL[prec] and ep <= TOL[prec]
+
+
+def test_max_size_source_set():
+    """16 sinks against 2^30 sources: the source range split into 256 ranges
+    of 2^22 with FP64 partials, and the workspace that
+    nbody_workspace_size(NB_OP_ACCEL, 2^30) reports; every sink against the
+    oracle, with the potential."""
+    from nbody_inputs import plummer_positions_device
+    prec = "mix_tilec"
+    xj = plummer_positions_device(MAX_N, 404, DEV)
+    mj = torch.full((MAX_N,), 2.0 ** -30, dtype=torch.float32, device=DEV)
+    xi = plummer_positions_device(16, 405, DEV)
+    eps = 2.0 ** -10
+    a, pot = nb.accel(xi, mj, eps, prec=prec, xj=xj, potential=True)
+    ah, ph = host(a), host(pot)
+    xjh = xj.cpu().numpy()
+    del xj, mj
+    torch.cuda.empty_cache()
+    ref, rpot = oracle.accel(host(xi), np.full(MAX_N, 2.0 ** -30), eps, xj=xjh, potential=True)
+    e, ep = rel(ah, ref), rel(ph, rpot)
+    print("16 sinks x 2^30 sources: e_glob %.3g, potential %.3g" % (e, ep))
+    assert e <= TOL[prec] and ep <= TOL[prec]
