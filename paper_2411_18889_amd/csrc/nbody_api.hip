@@ -140,7 +140,13 @@ std::vector<GraphEntry> g_graphs;
 uint64_t g_graph_clock = 0;
 hipStream_t g_capture_stream[64] = {};
 
-bool same_key(const StepKey& a, const StepKey& b) { return memcmp(&a, &b, sizeof(StepKey)) == 0; }
+// Field by field: a copied key need not carry its padding bytes along.
+bool same_key(const StepKey& a, const StepKey& b) {
+    return a.dev == b.dev && a.prec == b.prec && a.flags == b.flags && a.n == b.n &&
+           a.nsteps == b.nsteps && a.ckpt_every == b.ckpt_every && a.x == b.x && a.v == b.v &&
+           a.m == b.m && a.acc == b.acc && a.ckpt == b.ckpt && a.ws == b.ws &&
+           a.ws_bytes == b.ws_bytes && a.eps == b.eps && a.G == b.G && a.dt == b.dt;
+}
 
 // Waits for the entry's last launch, then frees it. Caller holds g_graph_mu.
 hipError_t release_graph(GraphEntry& g) {
