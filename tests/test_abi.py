@@ -238,3 +238,28 @@ def test_pass_info(L):
     assert L.nbody_pass_info(1, 0, TILEC, ctypes.byref(info)) == NB_EINVAL
     assert L.nbody_pass_info(1, 1000, 17, ctypes.byref(info)) == NB_EUNSUPPORTED
     assert L.nbody_pass_info(1, 1000, TILEC, None) == NB_EINVAL
+
+
+def test_plain_c_consumer(tmp_path):
+    """The headers compile as strict C99 and as C++, and a C program linked
+    against libnbody.so (no Python, no torch) gets the same answers from the
+    host-only entry points and the argument validation."""
+    import os
+    import shutil
+    if shutil.which("gcc") is None or shutil.which("g++") is None:
+        pytest.skip("no host C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    inc = os.path.join(root, "include")
+    libdir = os.path.dirname(_lib.LIB_PATH)
+    exe = str(tmp_path / "abi_consumer")
+    cc = ["gcc", "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", inc,
+          os.path.join(root, "tests", "c", "abi_consumer.c"), "-L", libdir, "-lnbody",
+          "-Wl,-rpath," + libdir, "-Wl,-rpath-link,/opt/rocm/lib", "-o", exe]
+    r = subprocess.run(cc, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run(["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++",
+                        "-I", inc, "-"], input='#include "diffusion3d.h"\n#include "nbody.h"\n',
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout, r.stderr)
