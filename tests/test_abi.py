@@ -16,7 +16,7 @@ from paper_2411_18889_amd._lib import (NB_EINVAL, NB_ENODEV, NB_EUNSUPPORTED, NB
                                        NB_OK, nb_launch)
 
 P = ctypes.c_void_p
-A = P(0x100000)  # fake, aligned device addresses; never reached
+A = P(0x100000)  # placeholder aligned addresses, for calls that must stop in validation
 B = P(0x200000)
 C = P(0x300000)
 D = P(0x400000)
@@ -26,6 +26,15 @@ F64, F32, TILEC = 0, 1, 5
 @pytest.fixture(scope="module")
 def L():
     return _lib.lib()
+
+
+@pytest.fixture
+def Lv(L):
+    """The library, for tests that hand it placeholder pointers: they are
+    meant for a host without a GPU (where nothing can be launched); with a
+    device present they are skipped."""
+    _skip_if_device(L)
+    return L
 
 
 def test_every_declared_symbol_is_exported(L):
@@ -88,7 +97,17 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 1 << 21, TILEC) < 1 << 30  # one-sided kernel
 
 
-def test_accel_workspace_covers_every_set_size(L):
+def _skip_if_device(L):
+    """Calls whose arguments pass validation launch kernels when a device is
+    present; with the placeholder pointers of these tests that would be an
+    access to memory nobody allocated. Such checks run only without a GPU."""
+    buf = ctypes.create_string_buffer(128)
+    if L.nbody_device_info(buf, 128) != NB_ENODEV:
+        pytest.skip("a GPU is present: valid calls would launch on placeholder pointers")
+
+
+def test_accel_workspace_covers_every_set_size(Lv):
+    L = Lv
     """nbody_workspace_size(NB_OP_ACCEL, max(ni, nj)) is enough for every
     ni, nj up to it. Checked through the library's own validation, which
     rejects a short workspace (NB_EWORKSPACE) before it looks for a device,
@@ -118,7 +137,8 @@ def _accel(L, ni=64, xi=A, nj=64, xj=B, mj=C, eps=0.1, G=1.0, prec=F64, acc=D, p
     return L.nbody_accel(ni, xi, nj, xj, mj, eps, G, prec, acc, pot, ws, wsb, None)
 
 
-def test_accel_validation(L):
+def test_accel_validation(Lv):
+    L = Lv
     assert _accel(L, ni=0) == NB_EINVAL
     assert _accel(L, nj=0) == NB_EINVAL
     assert _accel(L, ni=(1 << 30) + 1) == NB_EINVAL
@@ -143,6 +163,9 @@ def test_accel_workspace_checked_before_device(L):
     args = dict(ni=4096, nj=4096, xi=P(0x1000000), xj=P(0x2000000), mj=P(0x3000000),
                 acc=P(0x4000000), prec=TILEC)
     assert _accel(L, **args) == NB_EWORKSPACE
+    assert _accel(L, ws=P(0x5000000), wsb=1024, **args) == NB_EWORKSPACE
+    assert _accel(L, ws=P(0x5000000 + 128), wsb=bound, **args) == NB_EWORKSPACE  # not 256-aligned
+    _skip_if_device(L)
     assert _accel(L, ws=P(0x5000000), wsb=bound, **args) == NB_ENODEV
     # the exact need of this call, found through the validation itself:
     # 16 source ranges x 4 FP64 partials per sink
@@ -155,7 +178,8 @@ def test_accel_workspace_checked_before_device(L):
     assert _accel(L, ws=P(0x5000000 + 128), wsb=hi, **args) == NB_EWORKSPACE  # not 256-aligned
 
 
-def test_accel_ex_rejects_bad_shapes(L):
+def test_accel_ex_rejects_bad_shapes(Lv):
+    L = Lv
     for shape in ((3, 256, 1), (2, 96, 1), (2, 256, 0x1000), (2, 2048, 1)):
         ln = nb_launch(*shape)
         st = L.nbody_accel_ex(64, A, 64, B, C, 0.1, 1.0, F64, D, None, ctypes.byref(ln), None,
@@ -163,7 +187,8 @@ def test_accel_ex_rejects_bad_shapes(L):
         assert st == NB_EUNSUPPORTED, shape
 
 
-def test_step_validation(L):
+def test_step_validation(Lv):
+    L = Lv
     def step(n=64, x=A, v=B, m=C, acc=D, eps=0.1, dt=0.01, nsteps=1, prec=F64, flags=0,
              ckpt=None, every=0):
         return L.nbody_step(n, x, v, m, acc, eps, 1.0, dt, nsteps, prec, flags, ckpt, every,
@@ -179,7 +204,8 @@ def test_step_validation(L):
     assert step(prec=6) == NB_EUNSUPPORTED
 
 
-def test_adjoint_validation(L):
+def test_adjoint_validation(Lv):
+    L = Lv
     E, Fp, Gp = P(0x500000), P(0x600000), P(0x700000)
 
     def adj(n=64, lam_m=Gp, flags=0, ckpt=None, every=0, step_end=0, nsteps=1):
@@ -191,7 +217,8 @@ def test_adjoint_validation(L):
     assert adj(ckpt=P(0x900000), every=4, step_end=0, nsteps=1) == NB_EINVAL  # step_end < nsteps
 
 
-def test_diag_validation(L):
+def test_diag_validation(Lv):
+    L = Lv
     assert L.nbody_diag(0, A, B, C, 0.1, 1.0, F64, D, None, 0, None) == NB_EINVAL
     assert L.nbody_diag(64, A, B, C, 0.1, 1.0, F64, None, None, 0, None) == NB_EINVAL
     assert L.nbody_diag(64, A, B, C, 0.1, 1.0, F64, D, None, 0, None) == NB_EWORKSPACE
@@ -199,16 +226,15 @@ def test_diag_validation(L):
 
 def test_no_device_is_reported():
     L = _lib.lib()
-    buf = ctypes.create_string_buffer(128)
-    if L.nbody_device_info(buf, 128) != NB_ENODEV:
-        pytest.skip("a GPU is present")
+    _skip_if_device(L)
     # valid arguments: the call gets as far as the device check and stops there
     assert _accel(L) == NB_ENODEV
     assert L.nbody_step(64, A, B, C, D, 0.1, 1.0, 0.01, 1, F64, 0, None, 0, None, 0, None) == NB_ENODEV
     assert L.nbody_step(64, A, B, C, D, 0.1, 1.0, 0.01, 1, F64, 0x2, None, 0, None, 0, None) == NB_ENODEV
 
 
-def test_diffusion_validation(L):
+def test_diffusion_validation(Lv):
+    L = Lv
     def step(nx=8, ny=8, nz=8, dx=1.0, dy=1.0, dz=1.0, dt=0.1, kappa=1.0, f=A, fn=B):
         return L.diffusion3d_step(nx, ny, nz, dx, dy, dz, dt, kappa, f, fn, None)
     assert step(nx=0) == NB_EINVAL
@@ -240,7 +266,7 @@ def test_pass_info(L):
     assert L.nbody_pass_info(1, 1000, TILEC, None) == NB_EINVAL
 
 
-def test_plain_c_consumer(tmp_path):
+def test_plain_c_consumer(Lv, tmp_path):
     """The headers compile as strict C99 and as C++, and a C program linked
     against libnbody.so (no Python, no torch) gets the same answers from the
     host-only entry points and the argument validation."""
