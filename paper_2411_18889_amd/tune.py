@@ -36,6 +36,15 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _warm_up(fn, seconds=0.3):
+    import time
+    import torch
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        fn()
+        torch.cuda.synchronize()
+
+
 def tune(n, prec, eps=2.0 ** -8, shapes=None, reps=None, seed=5):
     import numpy as np
     import torch
@@ -53,7 +62,12 @@ def tune(n, prec, eps=2.0 ** -8, shapes=None, reps=None, seed=5):
     if reps is None:
         reps = max(2, min(200, int(2e11 // (n * n))))
     base = api.accel(X, M, eps, prec=prec)
-    t_lib = _time(lambda: api.accel(X, M, eps, prec=prec), reps)
+    # bring the clocks up before the first timing (the first shape timed on
+    # a cold GPU reads several per cent slow), and time the library's own
+    # choice again at the end: the better of the two is reported
+    lib_call = lambda: api.accel(X, M, eps, prec=prec)
+    _warm_up(lib_call)
+    t_lib = _time(lib_call, reps)
     if shapes is None:
         splits = sorted({1, 2, 4, 8, 16, 32, 64, 128} | {max(1, min(256, (4096 * 64) // max(1, n)))})
         shapes = list(itertools.product((1, 2, 4), (64, 128, 256, 512, 1024), splits))
@@ -74,6 +88,7 @@ def tune(n, prec, eps=2.0 ** -8, shapes=None, reps=None, seed=5):
         rows.append((ms, launch))
         if best is None or ms < best[0]:
             best = (ms, launch)
+    t_lib = min(t_lib, _time(lib_call, reps))
     rows.sort(key=lambda r: r[0])
     return {"n": n, "prec": prec, "best": best[1], "best_ms": best[0],
             "best_gpairs_per_s": n * n / best[0] / 1e6, "library_ms": t_lib,
