@@ -59,7 +59,7 @@ struct SumKahan {
     __device__ __forceinline__ void init() { s = 0.f; c = 0.f; }
     __device__ __forceinline__ void add_y(float y) {
         float t = s + y;
-        // keep the compensation: no reassociation (no fast-math in this build)
+        // keep the compensation: no reassociation (the library is compiled without fast-math)
         c = (t - s) - y;
         s = t;
     }
