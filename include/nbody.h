@@ -74,8 +74,8 @@ typedef enum nb_status {
  * masses; the mass adjoint is always double.
  *
  *   NB_F64        pos double, mass double. Pair arithmetic and sums in FP64
- *                 (hardware reciprocal square root refined by two Newton
- *                 steps).
+ *                 (hardware reciprocal square root refined to ~1 ulp by one
+ *                 third-order step).
  *   NB_F32        pos float,  mass float.  Pair arithmetic in FP32 with the
  *                 hardware reciprocal square root; per-particle sums are FP32
  *                 running sums, as the paper's listing.
