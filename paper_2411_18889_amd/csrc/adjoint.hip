@@ -176,6 +176,8 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(AdjArgs<Pol> a, int
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     double t[NQ] = {0, 0, 0, 0, 0, 0, 0};
+    // four ranges' loads in flight together, the adds in range order
+#pragma unroll 4
     for (int sp = 0; sp < nsplit; ++sp) {
         const double* q = a.part + (size_t)sp * NQ * a.n;
 #pragma unroll

@@ -234,6 +234,8 @@ __global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs 
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     double q[NQ] = {0, 0, 0, 0, 0, 0, 0};
+    // eight slots' loads in flight together, the adds in slot order
+#pragma unroll 8
     for (int k = 0; k < a.nb; ++k) {
         const float* p = a.part + (size_t)k * NQF * a.n + i;
 #pragma unroll

@@ -165,6 +165,8 @@ __global__ __launch_bounds__(256) void force_reduce_kernel(ForceArgs<Pol> a, int
     if (i >= a.ni) return;
     const size_t stride = (size_t)NQ * a.ni;
     double sx = 0, sy = 0, sz = 0, sp = 0;
+    // eight ranges' loads in flight together, the adds in range order
+#pragma unroll 8
     for (int s = 0; s < nsplit; ++s) {
         const double* q = a.part + s * stride;
         sx += q[i];

@@ -219,6 +219,9 @@ __global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs a) 
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+    // unrolled so that the loads of eight slots are in flight together (the
+    // adds stay in slot order); at small n the pass is latency-bound here
+#pragma unroll 8
     for (int k = 0; k < a.nb; ++k) {
         const float* p = a.part + (size_t)k * NQ * a.n;
         sx += double(p[i]);
