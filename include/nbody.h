@@ -30,7 +30,7 @@
  *   The pair sums run in one of two forms, chosen by n and the policy
  *   (nbody_pass_info reports which): a one-sided kernel (every sink sums all
  *   sources; optional split of the source range with FP64 partials), or, for
- *   NB_MIX_TILEC with one set acting on itself from 16384 particles, a
+ *   NB_MIX_TILEC with one set acting on itself from 12288 particles, a
  *   symmetric pass that evaluates each pair once for both bodies (Newton's
  *   third law) and adds FP32 partials per particle block in block order. No
  *   atomics in either: the same call on the same inputs gives bitwise the
@@ -286,7 +286,7 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
  *
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair, FP32
- * partials per block added in a fixed order (NB_MIX_TILEC from 16384
+ * partials per block added in a fixed order (NB_MIX_TILEC from 12288
  * particles while the partials fit a 16 GiB workspace). symmetric = 0: the
  * one-sided kernel in the shape (i_per_lane, block, split).
  */

@@ -280,9 +280,10 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // and grown, with more waves per workgroup, while the FP32 partials
     // (nb * 7 * n floats) would pass the workspace cap (blocks of 2048 at
     // 2^20); past the largest block the one-sided kernel is used.
-    // Below 16384 particles the one-sided kernel is as fast (measured: 3 %
-    // slower at 12288, 11 % faster at 16384, 21 % at 24576).
-    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    // Below 12288 particles the one-sided kernel is faster (measured, with the
+    // finishing kernel's loads overlapped: one-sided 31 % faster at 8192;
+    // symmetric 12 % faster at 12288, 21 % at 24576).
+    if (prec != NB_MIX_TILEC || n < 48 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
     static const SymShape cands[] = {{2, 2}, {4, 2}, {8, 2}, {16, 2}};  // 256 .. 2048
     constexpr int NC = 4;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };

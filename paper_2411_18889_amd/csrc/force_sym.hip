@@ -270,9 +270,10 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // and grown only when the FP32 partials (nb * 3 * n floats, or
     // nb * 4 * n with the potential) would pass
     // the workspace cap; past the largest block the one-sided kernel is used.
-    // Below 16384 particles the one-sided kernel is as fast (measured: 6 %
-    // slower at 12288, 10 % faster at 16384, 37 % at 24576).
-    if (prec != NB_MIX_TILEC || n < 64 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    // Below 12288 particles the one-sided kernel is faster (measured, with the
+    // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
+    // symmetric 23 % faster at 12288, 37 % at 24576).
+    if (prec != NB_MIX_TILEC || n < 48 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
     static const SymShape cands[] = {{2, 2}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 256 .. 4096
     constexpr int NC = 5;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };

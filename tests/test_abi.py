@@ -65,10 +65,11 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 4096, TILEC) > 0       # split source ranges: partials
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) > 0
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
-    # a set acting on itself with the tile-compensated policy from 16384 on:
+    # a set acting on itself with the tile-compensated policy from 12288 on:
     # the symmetric pass, one FP32 partial per particle, component and block
     # (blocks of at most min(n/48, 1024) particles, larger while the partials
     # would pass 16 GiB)
+    assert L.nbody_workspace_size(1, 12288, TILEC) == 48 * 3 * 12288 * 4
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
     assert L.nbody_workspace_size(1, 24576, TILEC) == 48 * 3 * 24576 * 4
     assert L.nbody_workspace_size(1, 32768, TILEC) == 64 * 3 * 32768 * 4
@@ -90,6 +91,7 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1_200_000, TILEC) == 1172 * 3 * 1_200_000 * 4
     # and the symmetric adjoint pass: seven FP32 partials per particle and
     # block (blocks of min(n/64, 512), larger while past 16 GiB, up to 2048)
+    assert L.nbody_workspace_size(2, 12288, TILEC) == 48 * 7 * 12288 * 4
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
     assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
@@ -260,6 +262,11 @@ def test_pass_info(L):
     assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
     assert L.nbody_pass_info(1, 1000, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
+    # the symmetric passes start at 12288 particles
+    for op in (1, 2):
+        assert L.nbody_pass_info(op, 12287, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
+        assert L.nbody_pass_info(op, 12288, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 1
+        assert info.block_particles == 256
     assert L.nbody_pass_info(0, 1000, TILEC, ctypes.byref(info)) == NB_EINVAL
     assert L.nbody_pass_info(1, 0, TILEC, ctypes.byref(info)) == NB_EINVAL
     assert L.nbody_pass_info(1, 1000, 17, ctypes.byref(info)) == NB_EUNSUPPORTED

@@ -80,9 +80,9 @@ def test_adjoint_fp32_pairs_matches_oracle(prec):
     assert max(errs) <= 1e-4
 
 
-@pytest.mark.parametrize("n", (16384 + 300, 32768, 32768 + 300))
+@pytest.mark.parametrize("n", (12288 + 5, 16384 + 300, 32768, 32768 + 300))
 def test_adjoint_symmetric_pass_matches_oracle(n):
-    """From 16384 particles on, the tile-compensated policy walks back with
+    """From 12288 particles on, the tile-compensated policy walks back with
     the symmetric (third-law) adjoint pass: blocks of n/64, ragged last
     blocks. Checked against the oracle's gradient and against the one-sided
     kernel (FP64-summed policy) on every particle."""

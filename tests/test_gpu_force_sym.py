@@ -1,6 +1,6 @@
 """GPU parity of the symmetric (third-law) force pass, which the library
 uses for one set acting on itself with the tile-compensated FP32 policy from
-16384 particles on: blocks of up to min(n/48, 1024) particles (2048 and 4096 when
+12288 particles on: blocks of up to min(n/48, 1024) particles (2048 and 4096 when
 the partials would pass 16 GiB), a work item per block pair, FP32 partials
 per block added in a fixed order.
 
@@ -22,8 +22,8 @@ pytestmark = pytest.mark.gpu
 PREC = "mix_tilec"
 TOL = 1e-5
 
-# blocks of 256 (16384 .. 24575), 512 and 1024; ragged last blocks and tiles
-SYM_NS = (16384, 16385, 20000, 24576 + 7, 32768, 32769, 32768 + 255, 40000, 65535, 65536,
+# blocks of 256 (12288 .. 24575), 512 and 1024; ragged last blocks and tiles
+SYM_NS = (12288, 12289, 14000, 16384, 16385, 20000, 24576 + 7, 32768, 32769, 32768 + 255, 40000, 65535, 65536,
           65536 + 1000, 131072 + 77)
 
 
