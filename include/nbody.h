@@ -287,7 +287,9 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair, FP32
  * partials per block added in a fixed order (NB_MIX_TILEC from 12288
- * particles while the partials fit a 16 GiB workspace). symmetric = 0: the
+ * particles; blocks grow while the partials would pass 16 GiB, and the
+ * largest block is used up to 64 GiB of partials: about 4.8 M particles for
+ * the force, 2.2 M for the adjoint). symmetric = 0: the
  * one-sided kernel in the shape (i_per_lane, block, split).
  */
 typedef struct nb_pass_info {

@@ -269,7 +269,10 @@ hipError_t launch_asym(const ASymArgs& a, bool force, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// As for the force pass: blocks grow while the partials pass 16 GiB, and
+// the largest block is used while its partials fit 64 GiB.
 constexpr size_t kAdjSymWorkspaceCap = size_t(16) << 30;
+constexpr size_t kAdjSymWorkspaceMax = size_t(64) << 30;
 
 }  // namespace
 
@@ -278,8 +281,9 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // sink already take ~126 VGPRs; four take ~254 and halve the waves per
     // SIMD) and blocks of 512 at N = 2^18; blocks are kept to at most n/64
     // and grown, with more waves per workgroup, while the FP32 partials
-    // (nb * 7 * n floats) would pass the workspace cap (blocks of 2048 at
-    // 2^20); past the largest block the one-sided kernel is used.
+    // (nb * 7 * n floats) would pass 16 GiB (blocks of 2048 at 2^20); the
+    // largest block serves up to 64 GiB of partials (about 2.2 M particles),
+    // the one-sided kernel the sizes beyond.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 31 % faster at 8192;
     // symmetric 12 % faster at 12288, 21 % at 24576).
@@ -290,6 +294,7 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 512 && bi(cands[k + 1]) <= n / 64) ++k;
     while (k < NC && adjoint_sym_partials_bytes(cands[k], n) > kAdjSymWorkspaceCap) ++k;
+    if (k == NC && adjoint_sym_partials_bytes(cands[NC - 1], n) <= kAdjSymWorkspaceMax) k = NC - 1;
     return k < NC ? cands[k] : SymShape{0, 0};
 }
 

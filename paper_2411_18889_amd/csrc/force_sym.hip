@@ -258,7 +258,12 @@ hipError_t launch_sym(const SymArgs& a, bool pot, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// Blocks grow while the partials pass kSymWorkspaceCap; where even the
+// largest block passes it, the largest is still used while its partials fit
+// kSymWorkspaceMax (under a quarter of the 288 GB of HBM), and only beyond
+// that the one-sided kernel takes over.
 constexpr size_t kSymWorkspaceCap = size_t(16) << 30;
+constexpr size_t kSymWorkspaceMax = size_t(64) << 30;
 
 }  // namespace
 
@@ -268,8 +273,9 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // the larger workgroups, and one source rotation per four pairs. Blocks
     // are kept to at most n/48 (>= 1176 equal work items for the 256 CUs),
     // and grown only when the FP32 partials (nb * 3 * n floats, or
-    // nb * 4 * n with the potential) would pass
-    // the workspace cap; past the largest block the one-sided kernel is used.
+    // nb * 4 * n with the potential) would pass 16 GiB; the largest block
+    // serves up to 64 GiB of partials (about 4.8 M particles), the one-sided
+    // kernel the sizes beyond.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
@@ -280,6 +286,7 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48) ++k;
     while (k < NC && sym_partials_bytes(cands[k], n, pot) > kSymWorkspaceCap) ++k;
+    if (k == NC && sym_partials_bytes(cands[NC - 1], n, pot) <= kSymWorkspaceMax) k = NC - 1;
     return k < NC ? cands[k] : SymShape{0, 0};
 }
 

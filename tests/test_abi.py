@@ -75,7 +75,9 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(1, 32768, TILEC) == 64 * 3 * 32768 * 4
     assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 1024 * 3 * (1 << 20) * 4
     assert L.nbody_workspace_size(1, 1 << 21, TILEC) == 512 * 3 * (1 << 21) * 4
-    assert L.nbody_workspace_size(1, 3 << 20, TILEC) < 1 << 30  # one-sided kernel
+    # past 16 GiB with the largest block (4096), the largest block up to 64 GiB
+    assert L.nbody_workspace_size(1, 3 << 20, TILEC) == 768 * 3 * (3 << 20) * 4
+    assert L.nbody_workspace_size(1, 5 << 20, TILEC) < 1 << 30  # one-sided kernel
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
     # nbody_accel covers the symmetric pass with the potential too: four
     # partials per particle and block, the block grown by the same bound
@@ -96,7 +98,8 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
     assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
     assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 512 * 7 * (1 << 20) * 4
-    assert L.nbody_workspace_size(2, 1 << 21, TILEC) < 1 << 30  # one-sided kernel
+    assert L.nbody_workspace_size(2, 1 << 21, TILEC) == 1024 * 7 * (1 << 21) * 4
+    assert L.nbody_workspace_size(2, 3 << 20, TILEC) < 1 << 30  # one-sided kernel
 
 
 def _skip_if_device(L):
