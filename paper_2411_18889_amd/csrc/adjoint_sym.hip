@@ -269,9 +269,11 @@ hipError_t launch_asym(const ASymArgs& a, bool force, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// As for the force pass: blocks grow while the partials pass 16 GiB, and
-// the largest block is used while its partials fit 64 GiB.
-constexpr size_t kAdjSymWorkspaceCap = size_t(16) << 30;
+// Blocks grow while the partials pass 32 GiB, and the largest block is used
+// while its partials fit 64 GiB. (At 2^20 blocks of 1024 -- 30 GB of
+// partials -- run 4 % faster with the force sums and 10 % without them than
+// blocks of 2048 with 15 GB; blocks of 512, 60 GB, gain nothing more.)
+constexpr size_t kAdjSymWorkspaceCap = size_t(32) << 30;
 constexpr size_t kAdjSymWorkspaceMax = size_t(64) << 30;
 
 }  // namespace
@@ -281,7 +283,7 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // sink already take ~126 VGPRs; four take ~254 and halve the waves per
     // SIMD) and blocks of 512 at N = 2^18; blocks are kept to at most n/64
     // and grown, with more waves per workgroup, while the FP32 partials
-    // (nb * 7 * n floats) would pass 16 GiB (blocks of 2048 at 2^20); the
+    // (nb * 7 * n floats) would pass 32 GiB (blocks of 1024 at 2^20); the
     // largest block serves up to 64 GiB of partials (about 2.2 M particles),
     // the one-sided kernel the sizes beyond.
     // Below 12288 particles the one-sided kernel is faster (measured, with the

@@ -92,12 +92,12 @@ def test_workspace_size(L):
     # and the pass without it still 1172 x 3)
     assert L.nbody_workspace_size(0, 1_200_000, TILEC) == 1172 * 3 * 1_200_000 * 4
     # and the symmetric adjoint pass: seven FP32 partials per particle and
-    # block (blocks of min(n/64, 512), larger while past 16 GiB, up to 2048)
+    # block (blocks of min(n/64, 512), larger while past 32 GiB, up to 2048)
     assert L.nbody_workspace_size(2, 12288, TILEC) == 48 * 7 * 12288 * 4
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
     assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
-    assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 512 * 7 * (1 << 20) * 4
+    assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 1024 * 7 * (1 << 20) * 4
     assert L.nbody_workspace_size(2, 1 << 21, TILEC) == 1024 * 7 * (1 << 21) * 4
     assert L.nbody_workspace_size(2, 3 << 20, TILEC) < 1 << 30  # one-sided kernel
 
@@ -261,7 +261,7 @@ def test_pass_info(L):
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
     assert info.workspace_bytes == L.nbody_workspace_size(1, 1 << 20, TILEC)
     assert L.nbody_pass_info(2, 1 << 20, TILEC, ctypes.byref(info)) == 0
-    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 1024, 2, 2048)
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 512, 2, 1024)
     assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
     assert L.nbody_pass_info(1, 1000, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0

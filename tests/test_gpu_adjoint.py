@@ -100,11 +100,11 @@ def test_adjoint_symmetric_pass_matches_oracle(n):
 
 @pytest.mark.parametrize("n", (600_000, 1 << 20, (1 << 21) + 3))
 def test_adjoint_symmetric_large_blocks(n):
-    """Sizes whose partials need blocks of 1024 (8 waves) and 2048 (16
-    waves), and 2^21 + 3, where even blocks of 2048 leave 60 GB of partials
-    (past 16 GiB, within the 64 GiB the largest block may take): one step
-    forward and back, against the one-sided kernel with the FP64-summed
-    policy on every particle."""
+    """Blocks of 512 (600,000), of 1024 (8 waves; 2^20, whose partials
+    would pass 32 GiB with blocks of 512), and 2^21 + 3, where even blocks of
+    2048 (16 waves) leave 60 GB of partials, within the 64 GiB the largest
+    block may take: one step forward and back, against the one-sided kernel
+    with the FP64-summed policy on every particle."""
     S, K = 1, 1
     x, v, m, y = _problem(n, 95)
     eps, dt = 2.0 ** -10, 2.0 ** -11
