@@ -30,7 +30,8 @@
  *   The pair sums run in one of two forms, chosen by n and the policy
  *   (nbody_pass_info reports which): a one-sided kernel (every sink sums all
  *   sources; optional split of the source range with FP64 partials), or, for
- *   NB_MIX_TILEC with one set acting on itself from 12288 particles, a
+ *   NB_MIX_TILEC and NB_F32 with one set acting on itself from 12288
+ *   particles (the adjoint: NB_MIX_TILEC only), a
  *   symmetric pass that evaluates each pair once for both bodies (Newton's
  *   third law) and adds FP32 partials per particle block in block order. No
  *   atomics in either: the same call on the same inputs gives bitwise the
@@ -78,7 +79,9 @@ typedef enum nb_status {
  *                 third-order step).
  *   NB_F32        pos float,  mass float.  Pair arithmetic in FP32 with the
  *                 hardware reciprocal square root; per-particle sums are FP32
- *                 running sums, as the paper's listing.
+ *                 running sums, as the paper's listing (in the symmetric
+ *                 pass, for a set on itself from 12288 particles, FP32 sums
+ *                 over each source block, then over the blocks in FP32).
  *   NB_MIX_ACC32  pos double, mass float. Positions are rounded to FP32 for
  *                 the pair arithmetic (FP32, as NB_F32); FP32 running sums.
  *                 Kick, drift and everything O(N) stay in FP64.
@@ -286,8 +289,8 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
  *
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair, FP32
- * partials per block added in a fixed order (NB_MIX_TILEC from 12288
- * particles; blocks grow while the partials would pass 16 GiB, and the
+ * partials per block added in a fixed order (NB_MIX_TILEC, and NB_F32 for
+ * the force, from 12288 particles; blocks grow while the partials would pass 16 GiB, and the
  * largest block is used up to 64 GiB of partials: about 4.8 M particles for
  * the force, 2.2 M for the adjoint). symmetric = 0: the
  * one-sided kernel in the shape (i_per_lane, block, split).

@@ -1,5 +1,5 @@
 // Symmetric pair-force pass of Eq. (1) for one particle set acting on itself
-// (the tile-compensated FP32 policy), on gfx950.
+// (the tile-compensated and the plain FP32 policies), on gfx950.
 //
 // Newton's third law: the pair (i, j) exerts m_j d s^-3/2 on i and
 // -m_i d s^-3/2 on j (d = x_j - x_i), so one reciprocal square root and one
@@ -34,6 +34,11 @@
 //    sign change, the potential is symmetric). The diagonal items include
 //    the j = i term m_i / eps, which the finish kernel removes with the same
 //    FP32 product the pair loop formed.
+//  * two policies use it: the tile-compensated one (FP64 state; each group's
+//    FP32 i-side sum folded into FP64; the slots added in FP64) and plain
+//    FP32 (FP32 state; the i-side a running FP32 sum over the whole source
+//    block; the slots added in FP32): every sum of the latter stays FP32, as
+//    the policy asks, only blocked by the third-law structure.
 #include "common.h"
 
 namespace nb {
@@ -42,23 +47,36 @@ namespace {
 
 constexpr int TJ = 256;  // sources per LDS tile
 
+// pos_t: state type; sum_t: per-sink i-side sum; fin_t: type the finishing
+// kernel adds the slots in.
+template <class Pos, class Sum, class Fin>
+struct SymPol {
+    using pos_t = Pos;
+    using sum_t = Sum;
+    using fin_t = Fin;
+};
+using SymTileC = SymPol<double, SumTile, double>;
+using SymF32 = SymPol<float, SumPlain<float>, float>;
+
+template <class Pos>
 struct SymArgs {
-    const double *x, *y, *z;
+    const Pos *x, *y, *z;
     const float* m;
     int n, nb;
     float eps2;
     float* part;  // [nb][NQ][n], NQ = 3, or 4 with the potential
 };
 
+template <class Pos>
 struct SymFinishArgs {
     const float* part;
     const float* m;  // for the j = i potential term
     int n, nb;
     float eps2;
     double G;
-    double *ax, *ay, *az;
-    double* pot;           // or nullptr
-    double *vx, *vy, *vz;  // or nullptr
+    Pos *ax, *ay, *az;
+    Pos* pot;           // or nullptr
+    Pos *vx, *vy, *vz;  // or nullptr
     double h;
 };
 
@@ -79,10 +97,10 @@ __device__ __forceinline__ float from_next_lane(float v) {
 // sums of the group travel with their source, one lane down per step, so
 // after 64 steps lane l holds the sum of source l, which it stores in the
 // wave's LDS row jq[c][g*64 + l]. P adds the potential as a fourth quantity.
-template <int K, bool JSIDE, bool P>
+template <int K, bool JSIDE, bool P, class Sum>
 __device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, const float* xi,
                                          const float* yi, const float* zi, const float* mi,
-                                         SumTile (*s)[4], float eps2, int lane) {
+                                         Sum (*s)[4], float eps2, int lane) {
     for (int g = 0; g < TJ / 64; ++g) {
         const float4* row = rec[g] + lane;
         float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
@@ -133,8 +151,8 @@ __device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, co
     }
 }
 
-template <int W, int K, bool P>
-__global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
+template <class Pol, int W, int K, bool P>
+__global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<typename Pol::pos_t> a) {
     constexpr int NT = W * 64;
     constexpr int BI = NT * K;
     constexpr int NQ = P ? 4 : 3;
@@ -155,7 +173,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
     const int w = tid >> 6;
     const int ibase = I * BI + w * 64 * K + lane;
     float xi[K], yi[K], zi[K], mi[K];
-    SumTile s[K][4];
+    typename Pol::sum_t s[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
@@ -182,9 +200,11 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
         }
         __syncthreads();
         if (jside)
-            sym_tile<K, true, P>(rec, &jacc[w][0][0], xi, yi, zi, mi, s, a.eps2, lane);
+            sym_tile<K, true, P, typename Pol::sum_t>(rec, &jacc[w][0][0], xi, yi, zi, mi, s,
+                                                      a.eps2, lane);
         else
-            sym_tile<K, false, P>(rec, nullptr, xi, yi, zi, mi, s, a.eps2, lane);
+            sym_tile<K, false, P, typename Pol::sum_t>(rec, nullptr, xi, yi, zi, mi, s, a.eps2,
+                                                       lane);
         __syncthreads();
         if (jside) {
             // j side of this tile: the wave rows added in wave order (every
@@ -210,51 +230,106 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs a) {
     }
 }
 
-// Adds the nb partials of every particle in slot order (FP64), then stores
+// Adds the nb partials of every particle in slot order (in fin_t: FP64 for
+// the tile-compensated policy, FP32 for the FP32 one), then stores
 // a = G * sum and applies the optional half-kick v <- v + h a, with a as
 // stored; with P, also the potential -G (sum - m_i / eps).
-template <bool P>
-__global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs a) {
+template <class Pol, bool P>
+__global__ __launch_bounds__(256) void force_sym_finish_kernel(
+    SymFinishArgs<typename Pol::pos_t> a) {
+    using pos_t = typename Pol::pos_t;
+    using fin_t = typename Pol::fin_t;
     constexpr int NQ = P ? 4 : 3;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
-    double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+    fin_t sx = 0, sy = 0, sz = 0, sp = 0;
     // unrolled so that the loads of eight slots are in flight together (the
     // adds stay in slot order); at small n the pass is latency-bound here
 #pragma unroll 8
     for (int k = 0; k < a.nb; ++k) {
         const float* p = a.part + (size_t)k * NQ * a.n;
-        sx += double(p[i]);
-        sy += double(p[(size_t)a.n + i]);
-        sz += double(p[(size_t)2 * a.n + i]);
-        if (P) sp += double(p[(size_t)3 * a.n + i]);
+        sx += fin_t(p[i]);
+        sy += fin_t(p[(size_t)a.n + i]);
+        sz += fin_t(p[(size_t)2 * a.n + i]);
+        if (P) sp += fin_t(p[(size_t)3 * a.n + i]);
     }
     if (P) {
         // the j = i term as the pair loop formed it: m_i times the FP32
         // reciprocal square root of eps^2, one FP32 product
         const double self = double(a.m[i] * rsqrt_pair(a.eps2));
-        a.pot[i] = -a.G * (sp - self);
+        a.pot[i] = pos_t(-a.G * (double(sp) - self));
     }
-    const double ax = a.G * sx, ay = a.G * sy, az = a.G * sz;
+    const pos_t ax = pos_t(a.G * double(sx)), ay = pos_t(a.G * double(sy)),
+                az = pos_t(a.G * double(sz));
     a.ax[i] = ax;
     a.ay[i] = ay;
     a.az[i] = az;
-    if (a.vx) {
-        a.vx[i] = a.vx[i] + a.h * ax;
-        a.vy[i] = a.vy[i] + a.h * ay;
-        a.vz[i] = a.vz[i] + a.h * az;
+    if (a.vx) {  // the leapfrog's closing half-kick, in the state type
+        const pos_t h = pos_t(a.h);
+        a.vx[i] = a.vx[i] + h * ax;
+        a.vy[i] = a.vy[i] + h * ay;
+        a.vz[i] = a.vz[i] + h * az;
     }
 }
 
-template <int W, int K>
-hipError_t launch_sym(const SymArgs& a, bool pot, hipStream_t stream) {
+template <class Pol, int W, int K>
+hipError_t launch_sym(const SymArgs<typename Pol::pos_t>& a, bool pot, hipStream_t stream) {
     const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
     if (pot)
-        hipLaunchKernelGGL((force_sym_kernel<W, K, true>), dim3((unsigned)items), dim3(W * 64), 0,
-                           stream, a);
+        hipLaunchKernelGGL((force_sym_kernel<Pol, W, K, true>), dim3((unsigned)items), dim3(W * 64),
+                           0, stream, a);
     else
-        hipLaunchKernelGGL((force_sym_kernel<W, K, false>), dim3((unsigned)items), dim3(W * 64), 0,
-                           stream, a);
+        hipLaunchKernelGGL((force_sym_kernel<Pol, W, K, false>), dim3((unsigned)items),
+                           dim3(W * 64), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <class Pol>
+hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, double eps,
+                   double G, void* acc, void* ws, hipStream_t stream, void* kick_v,
+                   double kick_h, void* pot) {
+    using pos_t = typename Pol::pos_t;
+    const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
+    SymArgs<pos_t> a{};
+    const pos_t* p = static_cast<const pos_t*>(x);
+    a.x = p;
+    a.y = p + n;
+    a.z = p + 2 * n;
+    a.m = static_cast<const float*>(m);
+    a.n = (int)n;
+    a.nb = (int)((n + bi - 1) / bi);
+    a.eps2 = float(eps) * float(eps);
+    a.part = static_cast<float*>(ws);
+    hipError_t e = hipErrorInvalidValue;
+#define NB_SYM_CASE(WV, KV) \
+    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<Pol, WV, KV>(a, pot != nullptr, stream);
+    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+#undef NB_SYM_CASE
+    if (e != hipSuccess) return e;
+    SymFinishArgs<pos_t> f{};
+    f.part = a.part;
+    f.m = a.m;
+    f.n = a.n;
+    f.nb = a.nb;
+    f.eps2 = a.eps2;
+    f.G = G;
+    f.pot = static_cast<pos_t*>(pot);
+    pos_t* po = static_cast<pos_t*>(acc);
+    f.ax = po;
+    f.ay = po + n;
+    f.az = po + 2 * n;
+    if (kick_v) {
+        pos_t* pv = static_cast<pos_t*>(kick_v);
+        f.vx = pv;
+        f.vy = pv + n;
+        f.vz = pv + 2 * n;
+        f.h = kick_h;
+    }
+    const dim3 fg((unsigned)((n + 255) / 256));
+    if (pot)
+        hipLaunchKernelGGL((force_sym_finish_kernel<Pol, true>), fg, dim3(256), 0, stream, f);
+    else
+        hipLaunchKernelGGL((force_sym_finish_kernel<Pol, false>), fg, dim3(256), 0, stream, f);
     return hipGetLastError();
 }
 
@@ -279,7 +354,8 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
-    if (prec != NB_MIX_TILEC || n < 48 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
+    if ((prec != NB_MIX_TILEC && prec != NB_F32) || n < 48 * 256 || n > (int64_t(1) << 28))
+        return SymShape{0, 0};
     static const SymShape cands[] = {{2, 2}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 256 .. 4096
     constexpr int NC = 5;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
@@ -297,52 +373,15 @@ size_t sym_partials_bytes(const SymShape& s, int64_t n, bool pot) {
     return (size_t)nb * (pot ? 4 : 3) * (size_t)n * sizeof(float);
 }
 
-hipError_t launch_force_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
-                            double eps, double G, void* acc, void* ws, hipStream_t stream,
-                            void* kick_v, double kick_h, void* pot) {
-    const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
-    if (bi == 0) return hipErrorInvalidValue;
-    SymArgs a{};
-    const double* p = static_cast<const double*>(x);
-    a.x = p;
-    a.y = p + n;
-    a.z = p + 2 * n;
-    a.m = static_cast<const float*>(m);
-    a.n = (int)n;
-    a.nb = (int)((n + bi - 1) / bi);
-    a.eps2 = float(eps) * float(eps);
-    a.part = static_cast<float*>(ws);
-    hipError_t e = hipErrorInvalidValue;
-#define NB_SYM_CASE(WV, KV) \
-    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<WV, KV>(a, pot != nullptr, stream);
-    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
-#undef NB_SYM_CASE
-    if (e != hipSuccess) return e;
-    SymFinishArgs f{};
-    f.part = a.part;
-    f.m = a.m;
-    f.n = a.n;
-    f.nb = a.nb;
-    f.eps2 = a.eps2;
-    f.G = G;
-    f.pot = static_cast<double*>(pot);
-    double* po = static_cast<double*>(acc);
-    f.ax = po;
-    f.ay = po + n;
-    f.az = po + 2 * n;
-    if (kick_v) {
-        double* pv = static_cast<double*>(kick_v);
-        f.vx = pv;
-        f.vy = pv + n;
-        f.vz = pv + 2 * n;
-        f.h = kick_h;
-    }
-    const dim3 fg((unsigned)((n + 255) / 256));
-    if (pot)
-        hipLaunchKernelGGL(force_sym_finish_kernel<true>, fg, dim3(256), 0, stream, f);
-    else
-        hipLaunchKernelGGL(force_sym_finish_kernel<false>, fg, dim3(256), 0, stream, f);
-    return hipGetLastError();
+hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
+                            const void* m, double eps, double G, void* acc, void* ws,
+                            hipStream_t stream, void* kick_v, double kick_h, void* pot) {
+    if ((int64_t)sh.waves * sh.ipl == 0) return hipErrorInvalidValue;
+    if (prec == NB_MIX_TILEC)
+        return run_sym<SymTileC>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
+    if (prec == NB_F32)
+        return run_sym<SymF32>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace nb

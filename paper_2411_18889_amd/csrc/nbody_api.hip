@@ -244,7 +244,7 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
     if ((st = check_device()) != NB_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return hip_status(timed(NB_PROF_FORCE, s, [&] {
-        if (sym.waves) return launch_force_sym(sym, ni, xi, mj, eps, G, acc, ws, s, nullptr, 0.0, pot);
+        if (sym.waves) return launch_force_sym(prec, sym, ni, xi, mj, eps, G, acc, ws, s, nullptr, 0.0, pot);
         return launch_force(prec, sh, ni, xi, nj, xj, mj, eps, G, self_set, acc, pot, ws, s);
     }));
 }
@@ -300,7 +300,7 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
         auto force = [&](bool kick) {
             return timed(NB_PROF_FORCE, q, [&] {
                 if (sym.waves)
-                    return launch_force_sym(sym, n, x, m, eps, G, acc, ws, q, kick ? v : nullptr, h);
+                    return launch_force_sym(prec, sym, n, x, m, eps, G, acc, ws, q, kick ? v : nullptr, h);
                 return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, q,
                                     kick ? v : nullptr, h);
             });

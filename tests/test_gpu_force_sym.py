@@ -1,6 +1,6 @@
 """GPU parity of the symmetric (third-law) force pass, which the library
-uses for one set acting on itself with the tile-compensated FP32 policy from
-12288 particles on: blocks of up to min(n/48, 1024) particles (2048 and 4096 when
+uses for one set acting on itself with the tile-compensated and the plain
+FP32 policies from 12288 particles on: blocks of up to min(n/48, 1024) particles (2048 and 4096 when
 the partials would pass 16 GiB), a work item per block pair, FP32 partials
 per block added in a fixed order.
 
@@ -54,6 +54,38 @@ def test_sym_matches_oracle_and_one_sided(n):
     assert rel(a, c) <= TOL
     med, p99, mx = per_particle(a, c)
     assert p99 <= 1e-5, (med, p99, mx)
+
+
+@pytest.mark.parametrize("n", (12288, 12289, 20000, 40000, 65535, 65536 + 1000))
+def test_sym_f32_policy(n):
+    """The plain FP32 policy (FP32 state, every sum FP32) runs the same
+    symmetric pass from 12288 particles: against the oracle on the FP32
+    state (every sink up to 40000, sampled above), against the one-sided
+    FP32 kernel on every sink, bitwise reproducible, and with the potential
+    (which leaves the accelerations bitwise unchanged)."""
+    prec = "f32"
+    x, v, m = plummer_sphere(n, 270 + n % 83)
+    m = m * np.random.default_rng(n + 2).uniform(0.5, 1.5, size=n)
+    eps = 2.0 ** -8
+    xd, _, md = to_dev(x, v, m, prec)
+    assert nb.pass_info(1, n, prec)["symmetric"] == 1
+    a1 = nb.accel(xd, md, eps, prec=prec)
+    a, pot = nb.accel(xd, md, eps, prec=prec, potential=True)
+    assert torch.equal(a, a1)
+    ah, ph = host(a), host(pot)
+    xs, ms = host(xd), host(md)
+    if n <= 40000:
+        ra, rp = oracle.accel(xs, ms, eps, potential=True)
+        ea, ep = rel(ah, ra), rel(ph, rp)
+    else:
+        idx = sample_indices(xs, 1024, 64, seed=n)
+        ra, rp = oracle.accel_sampled(xs, ms, eps, idx, potential=True)
+        ea, ep = rel(ah[:, idx], ra), rel(ph[idx], rp)
+    print("n=%d f32 symmetric e_glob %.3g, potential %.3g" % (n, ea, ep))
+    assert ea <= TOL and ep <= TOL
+    c = host(nb.accel(xd, md, eps, prec=prec, launch={"i_per_lane": 2, "block": 256, "split": 4}))
+    assert rel(ah, c) <= TOL
+    assert torch.equal(nb.accel(xd, md, eps, prec=prec), a1)
 
 
 def test_sym_third_law_and_determinism():
