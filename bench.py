@@ -368,6 +368,15 @@ def main():
                   "shape": fpass,
                   "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
 
+    # what the counted HBM bytes are made of: the symmetric passes write one
+    # FP32 partial per particle, quantity and block (the workspace) and read
+    # it back in the finishing kernel -- the cost of a fixed-order reduction
+    # without atomics; the algorithmic bytes are the state in and out
+    for r, info in ((roof, apass if dom == "adjoint" else fpass), (force_roof, fpass)):
+        if info["symmetric"] and r["traffic"] is not None:
+            r["traffic_partials_written"] = info["workspace_bytes"]
+            r["traffic_per_launch_ms_tb_s"] = r["traffic"] / (r["avg_launch_ms"] * 1e-3) / 1e12
+
     clk = clocks.summary()
     if clk:
         # the same achieved rate against the peak scaled to the measured clock
