@@ -375,7 +375,7 @@ def main():
     for r, info in ((roof, apass if dom == "adjoint" else fpass), (force_roof, fpass)):
         if info["symmetric"] and r["traffic"] is not None:
             r["traffic_partials_written"] = info["workspace_bytes"]
-            r["traffic_per_launch_ms_tb_s"] = r["traffic"] / (r["avg_launch_ms"] * 1e-3) / 1e12
+            r["traffic_rate_tb_s"] = r["traffic"] / (r["avg_launch_ms"] * 1e-3) / 1e12
 
     clk = clocks.summary()
     if clk:
