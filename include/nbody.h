@@ -30,10 +30,11 @@
  *   The pair sums run in one of two forms, chosen by n and the policy
  *   (nbody_pass_info reports which): a one-sided kernel (every sink sums all
  *   sources; optional split of the source range with FP64 partials), or, for
- *   NB_MIX_TILEC and NB_F32 with one set acting on itself from 12288
+ *   NB_MIX_TILEC, NB_F32 and NB_F64 with one set acting on itself from 12288
  *   particles (the adjoint: NB_MIX_TILEC only), a
  *   symmetric pass that evaluates each pair once for both bodies (Newton's
- *   third law) and adds FP32 partials per particle block in block order. No
+ *   third law) and adds partials per particle block (FP32; FP64 for NB_F64)
+ *   in block order. No
  *   atomics in either: the same call on the same inputs gives bitwise the
  *   same results. Results of different forms or launch shapes differ by
  *   rounding only.
@@ -289,8 +290,8 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
  *
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair, FP32
- * partials per block added in a fixed order (NB_MIX_TILEC, and NB_F32 for
- * the force, from 12288 particles; blocks grow while the partials would pass 16 GiB, and the
+ * partials per block added in a fixed order (NB_MIX_TILEC, and NB_F32 and
+ * NB_F64 for the force, from 12288 particles; blocks grow while the partials would pass 16 GiB, and the
  * largest block is used up to 64 GiB of partials: about 4.8 M particles for
  * the force, 2.2 M for the adjoint). symmetric = 0: the
  * one-sided kernel in the shape (i_per_lane, block, split).

@@ -163,18 +163,18 @@ hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi
                         double G, bool self_set, void* acc, void* pot, void* ws,
                         hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0);
 
-// Symmetric (third-law) force pass of one set on itself, NB_MIX_TILEC and
-// NB_F32: blocks of waves*64*ipl particles; waves == 0 means "not used". pot:
+// Symmetric (third-law) force pass of one set on itself, NB_MIX_TILEC, NB_F32
+// and NB_F64: blocks of waves*64*ipl particles; waves == 0 means "not used". pot:
 // the pass also computes the potential (four partial quantities, not three).
 struct SymShape {
     int waves;  // wavefronts per workgroup
     int ipl;    // sinks per lane
 };
 SymShape choose_sym_shape(int prec, int64_t n, bool pot = false);
-size_t sym_partials_bytes(const SymShape& s, int64_t n, bool pot = false);
+size_t sym_partials_bytes(int prec, const SymShape& s, int64_t n, bool pot = false);
 // acc = a(x) (and with kick_v, v <- v + kick_h * acc; with pot, the
 // potential with the j = i term removed); ws holds
-// sym_partials_bytes(sh, n, pot != nullptr) bytes.
+// sym_partials_bytes(prec, sh, n, pot != nullptr) bytes.
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
                             const void* m, double eps, double G, void* acc, void* ws,
                             hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0,

@@ -47,36 +47,40 @@ namespace {
 
 constexpr int TJ = 256;  // sources per LDS tile
 
-// pos_t: state type; sum_t: per-sink i-side sum; fin_t: type the finishing
-// kernel adds the slots in.
-template <class Pos, class Sum, class Fin>
+// pos_t / mass_t: state and mass types; calc_t: pair arithmetic (also the
+// source-side sums and the partials); sum_t: per-sink i-side sum; fin_t:
+// type the finishing kernel adds the slots in.
+template <class Pos, class Mass, class Calc, class Sum, class Fin>
 struct SymPol {
     using pos_t = Pos;
+    using mass_t = Mass;
+    using calc_t = Calc;
     using sum_t = Sum;
     using fin_t = Fin;
 };
-using SymTileC = SymPol<double, SumTile, double>;
-using SymF32 = SymPol<float, SumPlain<float>, float>;
+using SymTileC = SymPol<double, float, float, SumTile, double>;
+using SymF32 = SymPol<float, float, float, SumPlain<float>, float>;
+using SymF64 = SymPol<double, double, double, SumPlain<double>, double>;
 
-template <class Pos>
+template <class Pol>
 struct SymArgs {
-    const Pos *x, *y, *z;
-    const float* m;
+    const typename Pol::pos_t *x, *y, *z;
+    const typename Pol::mass_t* m;
     int n, nb;
-    float eps2;
-    float* part;  // [nb][NQ][n], NQ = 3, or 4 with the potential
+    typename Pol::calc_t eps2;
+    typename Pol::calc_t* part;  // [nb][NQ][n], NQ = 3, or 4 with the potential
 };
 
-template <class Pos>
+template <class Pol>
 struct SymFinishArgs {
-    const float* part;
-    const float* m;  // for the j = i potential term
+    const typename Pol::calc_t* part;
+    const typename Pol::mass_t* m;  // for the j = i potential term
     int n, nb;
-    float eps2;
+    typename Pol::calc_t eps2;
     double G;
-    Pos *ax, *ay, *az;
-    Pos* pot;           // or nullptr
-    Pos *vx, *vy, *vz;  // or nullptr
+    typename Pol::pos_t *ax, *ay, *az;
+    typename Pol::pos_t* pot;           // or nullptr
+    typename Pol::pos_t *vx, *vy, *vz;  // or nullptr
     double h;
 };
 
@@ -90,6 +94,14 @@ __device__ __forceinline__ float from_next_lane(float v) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
 }
 
+// The same for a double: its two 32-bit halves travel separately.
+__device__ __forceinline__ double from_next_lane(double v) {
+    const int src = ((__lane_id() + 1) & 63) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // One tile of sources against the K sinks of this lane. The tile is held as
 // TJ/64 groups of 64 sources, each stored twice in a row (rec[g][0..127]), so
 // that lane l meets source (l + t) mod 64 of the group at step t by reading
@@ -97,31 +109,31 @@ __device__ __forceinline__ float from_next_lane(float v) {
 // sums of the group travel with their source, one lane down per step, so
 // after 64 steps lane l holds the sum of source l, which it stores in the
 // wave's LDS row jq[c][g*64 + l]. P adds the potential as a fourth quantity.
-template <int K, bool JSIDE, bool P, class Sum>
-__device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, const float* xi,
-                                         const float* yi, const float* zi, const float* mi,
-                                         Sum (*s)[4], float eps2, int lane) {
+template <int K, bool JSIDE, bool P, class Sum, class C>
+__device__ __forceinline__ void sym_tile(const typename Vec4<C>::type (*rec)[128], C* jq,
+                                         const C* xi, const C* yi, const C* zi, const C* mi,
+                                         Sum (*s)[4], C eps2, int lane) {
     for (int g = 0; g < TJ / 64; ++g) {
-        const float4* row = rec[g] + lane;
-        float cx = 0.f, cy = 0.f, cz = 0.f, cp = 0.f;
+        const typename Vec4<C>::type* row = rec[g] + lane;
+        C cx = C(0), cy = C(0), cz = C(0), cp = C(0);
 #pragma unroll 4
         for (int t = 0; t < 64; ++t) {
-            const float4 q = row[t];
+            const typename Vec4<C>::type q = row[t];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                const float dx = q.x - xi[k];
-                const float dy = q.y - yi[k];
-                const float dz = q.z - zi[k];
-                const float ss = fmat(dz, dz, fmat(dy, dy, fmat(dx, dx, eps2)));
-                const float r = rsqrt_pair(ss);
-                const float r3 = r * (r * r);
-                const float wj = r3 * q.w;
+                const C dx = q.x - xi[k];
+                const C dy = q.y - yi[k];
+                const C dz = q.z - zi[k];
+                const C ss = fmat(dz, dz, fmat(dy, dy, fmat(dx, dx, eps2)));
+                const C r = rsqrt_pair(ss);
+                const C r3 = r * (r * r);
+                const C wj = r3 * q.w;
                 s[k][0].add_fma(dx, wj);
                 s[k][1].add_fma(dy, wj);
                 s[k][2].add_fma(dz, wj);
                 if (P) s[k][3].add_fma(q.w, r);
                 if (JSIDE) {
-                    const float wi = r3 * mi[k];
+                    const C wi = r3 * mi[k];
                     cx = fmat(dx, wi, cx);
                     cy = fmat(dy, wi, cy);
                     cz = fmat(dz, wi, cz);
@@ -152,13 +164,15 @@ __device__ __forceinline__ void sym_tile(const float4 (*rec)[128], float* jq, co
 }
 
 template <class Pol, int W, int K, bool P>
-__global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<typename Pol::pos_t> a) {
+__global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
+    using C = typename Pol::calc_t;
+    using V4 = typename Vec4<C>::type;
     constexpr int NT = W * 64;
     constexpr int BI = NT * K;
     constexpr int NQ = P ? 4 : 3;
     static_assert(BI % TJ == 0, "a block must hold whole tiles");
-    __shared__ float4 rec[TJ / 64][128];
-    __shared__ float jacc[W][NQ][TJ];
+    __shared__ V4 rec[TJ / 64][128];
+    __shared__ C jacc[W][NQ][TJ];
 
     // item -> (I, J), I <= J, items ordered by J then I
     const int64_t item = blockIdx.x;
@@ -172,16 +186,16 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<typename Pol:
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int ibase = I * BI + w * 64 * K + lane;
-    float xi[K], yi[K], zi[K], mi[K];
+    C xi[K], yi[K], zi[K], mi[K];
     typename Pol::sum_t s[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
         const bool ok = i < a.n;
-        xi[k] = ok ? float(a.x[i]) : 0.f;
-        yi[k] = ok ? float(a.y[i]) : 0.f;
-        zi[k] = ok ? float(a.z[i]) : 0.f;
-        mi[k] = ok ? a.m[i] : 0.f;  // a padding sink adds exactly 0 to the j side
+        xi[k] = ok ? C(a.x[i]) : C(0);
+        yi[k] = ok ? C(a.y[i]) : C(0);
+        zi[k] = ok ? C(a.z[i]) : C(0);
+        mi[k] = ok ? C(a.m[i]) : C(0);  // a padding sink adds exactly 0 to the j side
         s[k][0].init();
         s[k][1].init();
         s[k][2].init();
@@ -193,18 +207,21 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<typename Pol:
     for (int jt = jb; jt < je; jt += TJ) {
         for (int q = tid; q < TJ; q += NT) {
             const int j = jt + q;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);  // zero-mass padding
-            if (j < je) p = make_float4(float(a.x[j]), float(a.y[j]), float(a.z[j]), a.m[j]);
+            V4 p;  // zero-mass padding past the end
+            p.x = j < je ? C(a.x[j]) : C(0);
+            p.y = j < je ? C(a.y[j]) : C(0);
+            p.z = j < je ? C(a.z[j]) : C(0);
+            p.w = j < je ? C(a.m[j]) : C(0);
             rec[q >> 6][q & 63] = p;
             rec[q >> 6][(q & 63) + 64] = p;
         }
         __syncthreads();
         if (jside)
-            sym_tile<K, true, P, typename Pol::sum_t>(rec, &jacc[w][0][0], xi, yi, zi, mi, s,
-                                                      a.eps2, lane);
+            sym_tile<K, true, P, typename Pol::sum_t, C>(rec, &jacc[w][0][0], xi, yi, zi, mi, s,
+                                                         a.eps2, lane);
         else
-            sym_tile<K, false, P, typename Pol::sum_t>(rec, nullptr, xi, yi, zi, mi, s, a.eps2,
-                                                       lane);
+            sym_tile<K, false, P, typename Pol::sum_t, C>(rec, nullptr, xi, yi, zi, mi, s,
+                                                          a.eps2, lane);
         __syncthreads();
         if (jside) {
             // j side of this tile: the wave rows added in wave order (every
@@ -212,7 +229,7 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<typename Pol:
             // (the force on j is minus the sum, its potential the sum)
             for (int q = tid; q < NQ * TJ; q += NT) {
                 const int c = q / TJ, jj = q - c * TJ;
-                float sum = 0.f;
+                C sum = C(0);
 #pragma unroll
                 for (int v = 0; v < W; ++v) sum += jacc[v][c][jj];
                 const int j = jt + jj;
@@ -226,17 +243,16 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<typename Pol:
         const int i = ibase + k * 64;
         if (i >= a.n) continue;
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) a.part[((size_t)J * NQ + c) * a.n + i] = float(s[k][c].total());
+        for (int c = 0; c < NQ; ++c) a.part[((size_t)J * NQ + c) * a.n + i] = C(s[k][c].total());
     }
 }
 
 // Adds the nb partials of every particle in slot order (in fin_t: FP64 for
-// the tile-compensated policy, FP32 for the FP32 one), then stores
+// the tile-compensated and FP64 policies, FP32 for the FP32 one), then stores
 // a = G * sum and applies the optional half-kick v <- v + h a, with a as
 // stored; with P, also the potential -G (sum - m_i / eps).
 template <class Pol, bool P>
-__global__ __launch_bounds__(256) void force_sym_finish_kernel(
-    SymFinishArgs<typename Pol::pos_t> a) {
+__global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs<Pol> a) {
     using pos_t = typename Pol::pos_t;
     using fin_t = typename Pol::fin_t;
     constexpr int NQ = P ? 4 : 3;
@@ -247,15 +263,15 @@ __global__ __launch_bounds__(256) void force_sym_finish_kernel(
     // adds stay in slot order); at small n the pass is latency-bound here
 #pragma unroll 8
     for (int k = 0; k < a.nb; ++k) {
-        const float* p = a.part + (size_t)k * NQ * a.n;
+        const typename Pol::calc_t* p = a.part + (size_t)k * NQ * a.n;
         sx += fin_t(p[i]);
         sy += fin_t(p[(size_t)a.n + i]);
         sz += fin_t(p[(size_t)2 * a.n + i]);
         if (P) sp += fin_t(p[(size_t)3 * a.n + i]);
     }
     if (P) {
-        // the j = i term as the pair loop formed it: m_i times the FP32
-        // reciprocal square root of eps^2, one FP32 product
+        // the j = i term as the pair loop formed it: m_i times the
+        // reciprocal square root of eps^2, one product in the pair type
         const double self = double(a.m[i] * rsqrt_pair(a.eps2));
         a.pot[i] = pos_t(-a.G * (double(sp) - self));
     }
@@ -273,7 +289,7 @@ __global__ __launch_bounds__(256) void force_sym_finish_kernel(
 }
 
 template <class Pol, int W, int K>
-hipError_t launch_sym(const SymArgs<typename Pol::pos_t>& a, bool pot, hipStream_t stream) {
+hipError_t launch_sym(const SymArgs<Pol>& a, bool pot, hipStream_t stream) {
     const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
     if (pot)
         hipLaunchKernelGGL((force_sym_kernel<Pol, W, K, true>), dim3((unsigned)items), dim3(W * 64),
@@ -289,24 +305,25 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
                    double G, void* acc, void* ws, hipStream_t stream, void* kick_v,
                    double kick_h, void* pot) {
     using pos_t = typename Pol::pos_t;
+    using calc_t = typename Pol::calc_t;
     const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
-    SymArgs<pos_t> a{};
+    SymArgs<Pol> a{};
     const pos_t* p = static_cast<const pos_t*>(x);
     a.x = p;
     a.y = p + n;
     a.z = p + 2 * n;
-    a.m = static_cast<const float*>(m);
+    a.m = static_cast<const typename Pol::mass_t*>(m);
     a.n = (int)n;
     a.nb = (int)((n + bi - 1) / bi);
-    a.eps2 = float(eps) * float(eps);
-    a.part = static_cast<float*>(ws);
+    a.eps2 = calc_t(eps) * calc_t(eps);
+    a.part = static_cast<calc_t*>(ws);
     hipError_t e = hipErrorInvalidValue;
 #define NB_SYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_sym<Pol, WV, KV>(a, pot != nullptr, stream);
     NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
 #undef NB_SYM_CASE
     if (e != hipSuccess) return e;
-    SymFinishArgs<pos_t> f{};
+    SymFinishArgs<Pol> f{};
     f.part = a.part;
     f.m = a.m;
     f.n = a.n;
@@ -354,23 +371,25 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
-    if ((prec != NB_MIX_TILEC && prec != NB_F32) || n < 48 * 256 || n > (int64_t(1) << 28))
+    if ((prec != NB_MIX_TILEC && prec != NB_F32 && prec != NB_F64) || n < 48 * 256 ||
+        n > (int64_t(1) << 28))
         return SymShape{0, 0};
     static const SymShape cands[] = {{2, 2}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 256 .. 4096
     constexpr int NC = 5;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48) ++k;
-    while (k < NC && sym_partials_bytes(cands[k], n, pot) > kSymWorkspaceCap) ++k;
-    if (k == NC && sym_partials_bytes(cands[NC - 1], n, pot) <= kSymWorkspaceMax) k = NC - 1;
+    while (k < NC && sym_partials_bytes(prec, cands[k], n, pot) > kSymWorkspaceCap) ++k;
+    if (k == NC && sym_partials_bytes(prec, cands[NC - 1], n, pot) <= kSymWorkspaceMax) k = NC - 1;
     return k < NC ? cands[k] : SymShape{0, 0};
 }
 
-size_t sym_partials_bytes(const SymShape& s, int64_t n, bool pot) {
+size_t sym_partials_bytes(int prec, const SymShape& s, int64_t n, bool pot) {
     if (s.waves == 0) return 0;
     const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
     const int64_t nb = (n + bi - 1) / bi;
-    return (size_t)nb * (pot ? 4 : 3) * (size_t)n * sizeof(float);
+    const size_t elem = prec == NB_F64 ? sizeof(double) : sizeof(float);  // partial type
+    return (size_t)nb * (pot ? 4 : 3) * (size_t)n * elem;
 }
 
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
@@ -381,6 +400,8 @@ hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void*
         return run_sym<SymTileC>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
     if (prec == NB_F32)
         return run_sym<SymF32>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
+    if (prec == NB_F64)
+        return run_sym<SymF64>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
     return hipErrorInvalidValue;
 }
 

@@ -239,7 +239,7 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
         if (!shape_supported(sh)) return NB_EUNSUPPORTED;
     }
     int st = check_ws(ws, ws_bytes,
-                      sym.waves ? sym_partials_bytes(sym, ni, pot != nullptr) : accel_ws(sh, ni));
+                      sym.waves ? sym_partials_bytes(prec, sym, ni, pot != nullptr) : accel_ws(sh, ni));
     if (st != NB_OK) return st;
     if ((st = check_device()) != NB_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -287,7 +287,7 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
     }
     const Shape sh = choose_force_shape(prec, n, n);
     const SymShape sym = choose_sym_shape(prec, n);
-    int st = check_ws(ws, ws_bytes, sym.waves ? sym_partials_bytes(sym, n) : accel_ws(sh, n));
+    int st = check_ws(ws, ws_bytes, sym.waves ? sym_partials_bytes(prec, sym, n) : accel_ws(sh, n));
     if (st != NB_OK) return st;
     if ((st = check_device()) != NB_OK) return st;
 
@@ -480,13 +480,13 @@ size_t nbody_workspace_size(int op, int64_t n, int prec) {
     switch (op) {
     case NB_OP_ACCEL: {  // any ni, nj <= n; either pass, with or without the potential
         const size_t a = std::max(accel_ws(choose_force_shape(prec, n, n), n), force_partials_bound(n));
-        const size_t b = sym_partials_bytes(choose_sym_shape(prec, n), n);
-        const size_t c = sym_partials_bytes(choose_sym_shape(prec, n, true), n, true);
+        const size_t b = sym_partials_bytes(prec, choose_sym_shape(prec, n), n);
+        const size_t c = sym_partials_bytes(prec, choose_sym_shape(prec, n, true), n, true);
         return std::max(a, std::max(b, c));
     }
     case NB_OP_STEP: {
         const SymShape sym = choose_sym_shape(prec, n);
-        return sym.waves ? sym_partials_bytes(sym, n) : accel_ws(choose_force_shape(prec, n, n), n);
+        return sym.waves ? sym_partials_bytes(prec, sym, n) : accel_ws(choose_force_shape(prec, n, n), n);
     }
     case NB_OP_ADJOINT: {
         const SymShape sym = choose_adjoint_sym_shape(prec, n);

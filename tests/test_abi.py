@@ -262,8 +262,13 @@ def test_pass_info(L):
     assert info.workspace_bytes == L.nbody_workspace_size(1, 1 << 20, TILEC)
     assert L.nbody_pass_info(2, 1 << 20, TILEC, ctypes.byref(info)) == 0
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 512, 2, 1024)
-    assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
+    assert L.nbody_pass_info(1, 1 << 20, 2, ctypes.byref(info)) == 0  # FP32 running sums
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
+    # FP64: FP64 partials, so the blocks grow to 2048 at 2^20 to stay within 16 GiB
+    assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block_particles) == (1, 2048)
+    assert info.workspace_bytes == 512 * 3 * (1 << 20) * 8
+    assert L.nbody_pass_info(2, 1 << 20, F64, ctypes.byref(info)) == 0 and info.symmetric == 0
     assert L.nbody_pass_info(1, 1000, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
     # the symmetric passes start at 12288 particles
     for op in (1, 2):

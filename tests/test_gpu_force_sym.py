@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 
 PREC = "mix_tilec"
 TOL = 1e-5
+TOLS = {"f32": 1e-5, "f64": 1e-12}
 
 # blocks of 256 (12288 .. 24575), 512 and 1024; ragged last blocks and tiles
 SYM_NS = (12288, 12289, 14000, 16384, 16385, 20000, 24576 + 7, 32768, 32769, 32768 + 255, 40000, 65535, 65536,
@@ -56,14 +57,17 @@ def test_sym_matches_oracle_and_one_sided(n):
     assert p99 <= 1e-5, (med, p99, mx)
 
 
-@pytest.mark.parametrize("n", (12288, 12289, 20000, 40000, 65535, 65536 + 1000))
-def test_sym_f32_policy(n):
-    """The plain FP32 policy (FP32 state, every sum FP32) runs the same
-    symmetric pass from 12288 particles: against the oracle on the FP32
-    state (every sink up to 40000, sampled above), against the one-sided
-    FP32 kernel on every sink, bitwise reproducible, and with the potential
-    (which leaves the accelerations bitwise unchanged)."""
-    prec = "f32"
+@pytest.mark.parametrize("prec,n", [(p, n) for p in ("f32", "f64")
+                                    for n in (12288, 12289, 20000, 40000, 65535, 65536 + 1000)])
+def test_sym_f32_f64_policies(prec, n):
+    """The plain FP32 policy (FP32 state, every sum FP32) and the FP64 one
+    (FP64 pair arithmetic, FP64 source-side sums through the lanes, FP64
+    partials) run the same symmetric pass from 12288 particles: against the
+    oracle on the same state (every sink up to 40000, sampled above; 1e-5
+    and 1e-12), against the one-sided kernel on every sink, bitwise
+    reproducible, and with the potential (which leaves the accelerations
+    bitwise unchanged)."""
+    tol = TOLS[prec]
     x, v, m = plummer_sphere(n, 270 + n % 83)
     m = m * np.random.default_rng(n + 2).uniform(0.5, 1.5, size=n)
     eps = 2.0 ** -8
@@ -81,10 +85,10 @@ def test_sym_f32_policy(n):
         idx = sample_indices(xs, 1024, 64, seed=n)
         ra, rp = oracle.accel_sampled(xs, ms, eps, idx, potential=True)
         ea, ep = rel(ah[:, idx], ra), rel(ph[idx], rp)
-    print("n=%d f32 symmetric e_glob %.3g, potential %.3g" % (n, ea, ep))
-    assert ea <= TOL and ep <= TOL
+    print("n=%d %s symmetric e_glob %.3g, potential %.3g" % (n, prec, ea, ep))
+    assert ea <= tol and ep <= tol
     c = host(nb.accel(xd, md, eps, prec=prec, launch={"i_per_lane": 2, "block": 256, "split": 4}))
-    assert rel(ah, c) <= TOL
+    assert rel(ah, c) <= tol
     assert torch.equal(nb.accel(xd, md, eps, prec=prec), a1)
 
 
@@ -130,19 +134,21 @@ def test_sym_two_clusters_far_apart():
         assert abs(mean_ax - sign * other / 20.0 ** 2) <= 3e-2 * other / 20.0 ** 2
 
 
-def test_sym_step_matches_oracle():
+@pytest.mark.parametrize("prec", ("mix_tilec", "f64"))
+def test_sym_step_matches_oracle(prec):
     """The leapfrog at n = 32768 (symmetric force with the closing half-kick
     in its finishing kernel) against the oracle's FP64 steps."""
     n, S = 32768, 3
     x, v, m = plummer_sphere(n, 230)
     eps, dt = 2.0 ** -7, 2.0 ** -8
-    xd, vd, md = to_dev(x, v, m, PREC)
+    xd, vd, md = to_dev(x, v, m, prec)
     acc = torch.empty_like(xd)
-    nb.step(xd, vd, md, acc, eps, dt, S, prec=PREC)
+    nb.step(xd, vd, md, acc, eps, dt, S, prec=prec)
     xo, vo, ao = oracle.kdk(x, v, host(md), eps, dt, S)
-    assert rel(host(xd), xo) <= 1e-9
-    assert rel(host(vd) - v, vo - v) <= 1e-5
-    assert rel(host(acc), ao) <= TOL
+    f64 = prec == "f64"
+    assert rel(host(xd), xo) <= (1e-14 if f64 else 1e-9)
+    assert rel(host(vd) - v, vo - v) <= (1e-12 if f64 else 1e-5)
+    assert rel(host(acc), ao) <= (1e-12 if f64 else TOL)
 
 
 @pytest.mark.parametrize("n", (1_200_000, (1 << 21) + 3))
