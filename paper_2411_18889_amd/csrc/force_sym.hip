@@ -1,5 +1,5 @@
 // Symmetric pair-force pass of Eq. (1) for one particle set acting on itself
-// (the tile-compensated and the plain FP32 policies), on gfx950.
+// (the tile-compensated, plain FP32 and FP64 policies), on gfx950.
 //
 // Newton's third law: the pair (i, j) exerts m_j d s^-3/2 on i and
 // -m_i d s^-3/2 on j (d = x_j - x_i), so one reciprocal square root and one
@@ -33,12 +33,15 @@
 //    fourth quantity: m_j / r on the i side and m_i / r on the j side (no
 //    sign change, the potential is symmetric). The diagonal items include
 //    the j = i term m_i / eps, which the finish kernel removes with the same
-//    FP32 product the pair loop formed.
-//  * two policies use it: the tile-compensated one (FP64 state; each group's
-//    FP32 i-side sum folded into FP64; the slots added in FP64) and plain
-//    FP32 (FP32 state; the i-side a running FP32 sum over the whole source
-//    block; the slots added in FP32): every sum of the latter stays FP32, as
-//    the policy asks, only blocked by the third-law structure.
+//    product the pair loop formed.
+//  * three policies use it: the tile-compensated one (FP64 state, FP32 pair
+//    arithmetic; each group's FP32 i-side sum folded into FP64; FP32
+//    partials added in FP64), plain FP32 (FP32 state; the i-side a running
+//    FP32 sum over the whole source block; the slots added in FP32: every
+//    sum stays FP32, as the policy asks, only blocked by the third-law
+//    structure) and FP64 (FP64 records, pair arithmetic, source-side sums,
+//    partials and slot sums; the source-side sums rotate as two 32-bit
+//    halves). The description above says FP32 where it is the pair type.
 #include "common.h"
 
 namespace nb {
