@@ -289,12 +289,14 @@ size_t nbody_workspace_size(int op, int64_t n, int prec);
  * NULL out; NB_EUNSUPPORTED for an unknown prec.
  *
  * symmetric = 1: the third-law pass -- particles cut into blocks of
- * block_particles = block * i_per_lane, one workgroup per block pair, FP32
- * partials per block added in a fixed order (NB_MIX_TILEC, and NB_F32 and
- * NB_F64 for the force, from 12288 particles; blocks grow while the partials would pass 16 GiB, and the
- * largest block is used up to 64 GiB of partials: about 4.8 M particles for
- * the force, 2.2 M for the adjoint). symmetric = 0: the
- * one-sided kernel in the shape (i_per_lane, block, split).
+ * block_particles = block * i_per_lane, one workgroup per block pair,
+ * partials per block (FP32; FP64 for NB_F64) added in a fixed order
+ * (NB_MIX_TILEC, and NB_F32 and NB_F64 for the force, from 12288 particles;
+ * blocks grow while the partials would pass 16 GiB -- 32 GiB for the
+ * adjoint -- and the largest block is used up to 64 GiB of partials: about
+ * 4.8 M particles for the tile-compensated force, 2.2 M for the adjoint).
+ * symmetric = 0: the one-sided kernel in the shape (i_per_lane, block,
+ * split).
  */
 typedef struct nb_pass_info {
     int32_t symmetric;
