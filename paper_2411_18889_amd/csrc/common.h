@@ -158,10 +158,16 @@ size_t adjoint_partials_bytes(const Shape& s, int64_t n);
 // Force: acc (and pot) of ni sinks. self_set: xi and xj are the same set.
 // kick_v (optional, 3 ni pos elements): also apply v <- v + kick_h * acc in
 // the epilogue, with acc as stored (the leapfrog's closing half-kick).
+// drift_x (optional, with kick_v, self set): then also the next step's
+// kick and drift, v <- v + kick_h * acc; x <- x + drift_dt * v, when the
+// pass has a finishing kernel that runs after every read of x; *drifted
+// (if given) tells whether it did.
 hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi,
                         int64_t nj, const void* xj, const void* mj, double eps,
                         double G, bool self_set, void* acc, void* pot, void* ws,
-                        hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0);
+                        hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0,
+                        void* drift_x = nullptr, double drift_dt = 0.0,
+                        bool* drifted = nullptr);
 
 // Symmetric (third-law) force pass of one set on itself, NB_MIX_TILEC, NB_F32
 // and NB_F64: blocks of waves*64*ipl particles; waves == 0 means "not used". pot:
@@ -175,10 +181,13 @@ size_t sym_partials_bytes(int prec, const SymShape& s, int64_t n, bool pot = fal
 // acc = a(x) (and with kick_v, v <- v + kick_h * acc; with pot, the
 // potential with the j = i term removed); ws holds
 // sym_partials_bytes(prec, sh, n, pot != nullptr) bytes.
+// drift_x / drift_dt / drifted: as launch_force (the finishing kernel always
+// runs after the pair kernel, so the drift is always taken when asked for).
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
                             const void* m, double eps, double G, void* acc, void* ws,
                             hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0,
-                            void* pot = nullptr);
+                            void* pot = nullptr, void* drift_x = nullptr,
+                            double drift_dt = 0.0, bool* drifted = nullptr);
 
 // Fused adjoint pair pass at x with adjoint lam_v: computes a(x), J^T lam_v,
 // G^T lam_v and applies the epilogue

@@ -45,6 +45,8 @@ struct ForceArgs {
     pos_t *ax, *ay, *az, *pot;  // final outputs (part == nullptr)
     pos_t *vx, *vy, *vz;  // velocities to kick, or nullptr
     double h;             // kick: v <- v + h a, with a as stored
+    pos_t *dx, *dy, *dz;  // with vx: positions of the next step's drift, or nullptr
+    double dt;            // drift: v <- v + h a; x <- x + dt v (after the kick)
     double* part;         // [nsplit][NQ][ni] FP64 partial sums, or nullptr
 };
 
@@ -59,9 +61,19 @@ __device__ __forceinline__ void finish_sink(const ForceArgs<Pol>& a, int i, doub
     a.az[i] = az;
     if (a.vx) {  // the leapfrog's closing half-kick, same arithmetic as the kick kernel
         const pos_t h = pos_t(a.h);
-        a.vx[i] = a.vx[i] + h * ax;
-        a.vy[i] = a.vy[i] + h * ay;
-        a.vz[i] = a.vz[i] + h * az;
+        pos_t vx = fmat(h, ax, a.vx[i]), vy = fmat(h, ay, a.vy[i]), vz = fmat(h, az, a.vz[i]);
+        if (a.dx) {  // and the next step's kick and drift, as the kick-drift kernel does them
+            const pos_t dt = pos_t(a.dt);
+            vx = fmat(h, ax, vx);
+            vy = fmat(h, ay, vy);
+            vz = fmat(h, az, vz);
+            a.dx[i] = fmat(dt, vx, a.dx[i]);
+            a.dy[i] = fmat(dt, vy, a.dy[i]);
+            a.dz[i] = fmat(dt, vz, a.dz[i]);
+        }
+        a.vx[i] = vx;
+        a.vy[i] = vy;
+        a.vz[i] = vz;
     }
     if (POT) {
         double self = 0.0;
@@ -229,14 +241,19 @@ hipError_t launch_any(const Shape& sh, ForceArgs<Pol> a, int nsplit, hipStream_t
 
 template <class Pol, bool ACC, bool POT>
 hipError_t run_force(const Shape& sh, ForceArgs<Pol> a, void* ws, bool partials_only,
-                     hipStream_t stream) {
+                     hipStream_t stream, bool* drifted = nullptr) {
     const int span = split_span(a.nj, sh.split, sh.block);
     const int nsplit = (a.nj + span - 1) / span;
     a.jspan = span;
     if (nsplit == 1 && !partials_only) {
+        // each workgroup finishes its own sinks while others may still read
+        // their positions as sources: no drift here
+        a.dx = a.dy = a.dz = nullptr;
+        if (drifted) *drifted = false;
         a.part = nullptr;
         return launch_any<Pol, ACC, POT>(sh, a, 1, stream);
     }
+    if (drifted) *drifted = a.dx != nullptr;
     a.part = static_cast<double*>(ws);
     hipError_t e = launch_any<Pol, ACC, POT>(sh, a, nsplit, stream);
     if (e != hipSuccess || partials_only) return e;
@@ -317,8 +334,9 @@ Shape choose_force_shape(int prec, int64_t ni, int64_t nj) {
 hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi, int64_t nj,
                         const void* xj, const void* mj, double eps, double G, bool self_set,
                         void* acc, void* pot, void* ws, hipStream_t stream, void* kick_v,
-                        double kick_h) {
+                        double kick_h, void* drift_x, double drift_dt, bool* drifted) {
     hipError_t err = hipErrorInvalidValue;
+    if (drifted) *drifted = false;
     dispatch_prec(prec, [&](auto tag) {
         using Pol = decltype(tag);
         using pos_t = typename Pol::pos_t;
@@ -329,9 +347,16 @@ hipError_t launch_force(int prec, const Shape& shape, int64_t ni, const void* xi
             a.vy = pv + ni;
             a.vz = pv + 2 * ni;
             a.h = kick_h;
+            if (drift_x && self_set) {
+                pos_t* px = static_cast<pos_t*>(drift_x);
+                a.dx = px;
+                a.dy = px + ni;
+                a.dz = px + 2 * ni;
+                a.dt = drift_dt;
+            }
         }
-        err = pot ? run_force<Pol, true, true>(shape, a, ws, false, stream)
-                  : run_force<Pol, true, false>(shape, a, ws, false, stream);
+        err = pot ? run_force<Pol, true, true>(shape, a, ws, false, stream, drifted)
+                  : run_force<Pol, true, false>(shape, a, ws, false, stream, drifted);
     });
     return err;
 }

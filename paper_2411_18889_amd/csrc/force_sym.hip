@@ -85,6 +85,8 @@ struct SymFinishArgs {
     typename Pol::pos_t* pot;           // or nullptr
     typename Pol::pos_t *vx, *vy, *vz;  // or nullptr
     double h;
+    typename Pol::pos_t *dx, *dy, *dz;  // with vx: the next step's drift, or nullptr
+    double dt;
 };
 
 // Lane l receives the value of lane (l + 1) mod 64, through the LDS
@@ -285,9 +287,19 @@ __global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs<Pol
     a.az[i] = az;
     if (a.vx) {  // the leapfrog's closing half-kick, in the state type
         const pos_t h = pos_t(a.h);
-        a.vx[i] = a.vx[i] + h * ax;
-        a.vy[i] = a.vy[i] + h * ay;
-        a.vz[i] = a.vz[i] + h * az;
+        pos_t vx = fmat(h, ax, a.vx[i]), vy = fmat(h, ay, a.vy[i]), vz = fmat(h, az, a.vz[i]);
+        if (a.dx) {  // and the next step's kick and drift, as the kick-drift kernel does them
+            const pos_t dt = pos_t(a.dt);
+            vx = fmat(h, ax, vx);
+            vy = fmat(h, ay, vy);
+            vz = fmat(h, az, vz);
+            a.dx[i] = fmat(dt, vx, a.dx[i]);
+            a.dy[i] = fmat(dt, vy, a.dy[i]);
+            a.dz[i] = fmat(dt, vz, a.dz[i]);
+        }
+        a.vx[i] = vx;
+        a.vy[i] = vy;
+        a.vz[i] = vz;
     }
 }
 
@@ -306,7 +318,7 @@ hipError_t launch_sym(const SymArgs<Pol>& a, bool pot, hipStream_t stream) {
 template <class Pol>
 hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, double eps,
                    double G, void* acc, void* ws, hipStream_t stream, void* kick_v,
-                   double kick_h, void* pot) {
+                   double kick_h, void* pot, void* drift_x, double drift_dt) {
     using pos_t = typename Pol::pos_t;
     using calc_t = typename Pol::calc_t;
     const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
@@ -344,6 +356,13 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
         f.vy = pv + n;
         f.vz = pv + 2 * n;
         f.h = kick_h;
+        if (drift_x) {
+            pos_t* px = static_cast<pos_t*>(drift_x);
+            f.dx = px;
+            f.dy = px + n;
+            f.dz = px + 2 * n;
+            f.dt = drift_dt;
+        }
     }
     const dim3 fg((unsigned)((n + 255) / 256));
     if (pot)
@@ -397,14 +416,20 @@ size_t sym_partials_bytes(int prec, const SymShape& s, int64_t n, bool pot) {
 
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
                             const void* m, double eps, double G, void* acc, void* ws,
-                            hipStream_t stream, void* kick_v, double kick_h, void* pot) {
+                            hipStream_t stream, void* kick_v, double kick_h, void* pot,
+                            void* drift_x, double drift_dt, bool* drifted) {
     if ((int64_t)sh.waves * sh.ipl == 0) return hipErrorInvalidValue;
+    if (!kick_v) drift_x = nullptr;
+    if (drifted) *drifted = drift_x != nullptr;
     if (prec == NB_MIX_TILEC)
-        return run_sym<SymTileC>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
+        return run_sym<SymTileC>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot,
+                                 drift_x, drift_dt);
     if (prec == NB_F32)
-        return run_sym<SymF32>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
+        return run_sym<SymF32>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot,
+                               drift_x, drift_dt);
     if (prec == NB_F64)
-        return run_sym<SymF64>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot);
+        return run_sym<SymF64>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot,
+                               drift_x, drift_dt);
     return hipErrorInvalidValue;
 }
 

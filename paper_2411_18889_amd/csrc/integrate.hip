@@ -24,9 +24,9 @@ __global__ __launch_bounds__(TPB) void kick_drift_kernel(T* __restrict__ x, T* _
                                                          int64_t count) {
     for (int64_t k = blockIdx.x * (int64_t)TPB + threadIdx.x; k < count;
          k += (int64_t)gridDim.x * TPB) {
-        const T vh = v[k] + h * a[k];
+        const T vh = fmat(h, a[k], v[k]);  // the same FMAs as the force epilogue's
         v[k] = vh;
-        x[k] = x[k] + dt * vh;
+        x[k] = fmat(dt, vh, x[k]);
     }
 }
 

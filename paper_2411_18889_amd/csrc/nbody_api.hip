@@ -295,14 +295,19 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
     const double h = 0.5 * dt;
     // Enqueues the whole loop on q.
     auto enqueue = [&](hipStream_t q) -> hipError_t {
-        // force(kick): a <- a(x), and with kick the closing half-kick
-        // v <- v + h a in the same launch (the pair pass never reads v)
-        auto force = [&](bool kick) {
+        // force(kick, drift): a <- a(x), and with kick the closing half-kick
+        // v <- v + h a in the same launch group (the pair pass never reads
+        // v); with drift also the next step's kick and drift, in the
+        // finishing kernel, where the pass has one (*drifted tells)
+        auto force = [&](bool kick, bool drift, bool* drifted) {
             return timed(NB_PROF_FORCE, q, [&] {
+                void* kv = kick ? v : nullptr;
+                void* dx = (kick && drift) ? x : nullptr;
                 if (sym.waves)
-                    return launch_force_sym(prec, sym, n, x, m, eps, G, acc, ws, q, kick ? v : nullptr, h);
-                return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, q,
-                                    kick ? v : nullptr, h);
+                    return launch_force_sym(prec, sym, n, x, m, eps, G, acc, ws, q, kv, h, nullptr,
+                                            dx, dt, drifted);
+                return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, q, kv,
+                                    h, dx, dt, drifted);
             });
         };
         auto store = [&](int64_t slot) -> hipError_t {
@@ -315,12 +320,20 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
             });
         };
         hipError_t e = hipSuccess;
-        if (!(flags & NB_ACC_VALID)) e = force(false);
+        if (!(flags & NB_ACC_VALID)) e = force(false, false, nullptr);
         if (e == hipSuccess && ckpt) e = store(0);
+        // a step's kick and drift run in the previous force pass's finishing
+        // kernel unless that pass ended the call or a checkpoint slot, whose
+        // stored state is the synchronised one
+        bool drifted = false;
         for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
-            e = timed(NB_PROF_UPDATE, q, [&] { return launch_kick_drift(prec, n, x, v, acc, h, dt, q); });
-            if (e == hipSuccess) e = force(true);
-            if (e == hipSuccess && ckpt && (k + 1) % ckpt_every == 0) e = store((k + 1) / ckpt_every);
+            if (!drifted)
+                e = timed(NB_PROF_UPDATE, q, [&] { return launch_kick_drift(prec, n, x, v, acc, h, dt, q); });
+            const bool stored = ckpt && (k + 1) % ckpt_every == 0;
+            const bool fuse = (k + 1 < nsteps) && !stored;
+            drifted = false;
+            if (e == hipSuccess) e = force(true, fuse, &drifted);
+            if (e == hipSuccess && stored) e = store((k + 1) / ckpt_every);
         }
         return e;
     };
