@@ -29,3 +29,9 @@ def test_clock_sampler_stops_and_summarises():
         assert s["samples"] >= 1
     c.samples = [2000.0, 2400.0]
     assert c.summary()["sclk_mhz_mean"] == 2200.0
+
+
+def test_tuner_cli_help():
+    r = subprocess.run([sys.executable, "-m", "paper_2411_18889_amd.tune", "--help"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 0 and "--n" in r.stdout and "--prec" in r.stdout
