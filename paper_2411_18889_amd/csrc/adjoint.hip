@@ -49,6 +49,9 @@ struct AdjArgs {
     pos_t *vx, *vy, *vz;   // velocity in/out (update_state)
     pos_t *gx, *gy, *gz;   // lam_x in/out
     double* gm;            // lam_m in/out
+    pos_t *rx, *ry, *rz;   // x of the next step's reverse drift, or nullptr
+    pos_t *rlx, *rly, *rlz;  // lam_v written by that drift
+    double dt;
     double* part;          // [nsplit][NQ][n] or nullptr
 };
 
@@ -66,9 +69,23 @@ __device__ __forceinline__ void finish_adj(const AdjArgs<Pol>& a, int i, const d
         a.ax[i] = ax;
         a.ay[i] = ay;
         a.az[i] = az;
-        a.vx[i] = a.vx[i] - h * ax;
-        a.vy[i] = a.vy[i] - h * ay;
-        a.vz[i] = a.vz[i] - h * az;
+        a.vx[i] = fmat(-h, ax, a.vx[i]);
+        a.vy[i] = fmat(-h, ay, a.vy[i]);
+        a.vz[i] = fmat(-h, az, a.vz[i]);
+    }
+    if (a.rx) {  // the next step's reverse drift, as the reverse-drift kernel does it
+        const pos_t h = pos_t(a.h), dt = pos_t(a.dt);
+        a.rlx[i] = fmat(dt, a.gx[i], a.rlx[i]);
+        a.rly[i] = fmat(dt, a.gy[i], a.rly[i]);
+        a.rlz[i] = fmat(dt, a.gz[i], a.rlz[i]);
+        const pos_t vx = fmat(-h, a.ax[i], a.vx[i]), vy = fmat(-h, a.ay[i], a.vy[i]),
+                    vz = fmat(-h, a.az[i], a.vz[i]);
+        a.vx[i] = vx;
+        a.vy[i] = vy;
+        a.vz[i] = vz;
+        a.rx[i] = fmat(-dt, vx, a.rx[i]);
+        a.ry[i] = fmat(-dt, vy, a.ry[i]);
+        a.rz[i] = fmat(-dt, vz, a.rz[i]);
     }
 }
 
@@ -243,8 +260,9 @@ size_t adjoint_partials_bytes(const Shape& s, int64_t n) {
 hipError_t launch_adjoint(int prec, const Shape& sh, int64_t n, const void* x, const void* m,
                           const void* lam_v, double eps, double G, double c, bool update_state,
                           double h, void* acc, void* v, void* lam_x, double* lam_m, void* ws,
-                          hipStream_t stream) {
+                          hipStream_t stream, void* drift_x, double drift_dt, bool* drifted) {
     hipError_t err = hipErrorInvalidValue;
+    if (drifted) *drifted = false;
     dispatch_prec(prec, [&](auto tag) {
         using Pol = decltype(tag);
         using pos_t = typename Pol::pos_t;
@@ -272,10 +290,18 @@ hipError_t launch_adjoint(int prec, const Shape& sh, int64_t n, const void* x, c
         const int span = split_span(n, sh.split, sh.block);
         const int nsplit = (int)((n + span - 1) / span);
         a.jspan = span;
-        if (nsplit == 1) {
+        if (nsplit == 1) {  // sinks finish while others still read x and lam_v: no drift
             a.part = nullptr;
             err = launch_any<Pol>(sh, a, 1, stream);
             return;
+        }
+        if (drift_x) {
+            pos_t* prx = static_cast<pos_t*>(drift_x);
+            pos_t* prl = static_cast<pos_t*>(const_cast<void*>(lam_v));
+            a.rx = prx; a.ry = prx + n; a.rz = prx + 2 * n;
+            a.rlx = prl; a.rly = prl + n; a.rlz = prl + 2 * n;
+            a.dt = drift_dt;
+            if (drifted) *drifted = true;
         }
         a.part = static_cast<double*>(ws);
         err = launch_any<Pol>(sh, a, nsplit, stream);

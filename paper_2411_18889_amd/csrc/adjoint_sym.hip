@@ -43,6 +43,9 @@ struct ASymFinishArgs {
     double *vx, *vy, *vz;
     double *gx, *gy, *gz;
     double* gm;
+    double *rx, *ry, *rz;     // x of the next step's reverse drift, or nullptr
+    double *rlx, *rly, *rlz;  // lam_v written by that drift
+    double dt;
 };
 
 // Lane l receives the value of lane (l + 1) mod 64, through the LDS
@@ -251,9 +254,23 @@ __global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs 
         a.ax[i] = ax;
         a.ay[i] = ay;
         a.az[i] = az;
-        a.vx[i] = a.vx[i] - a.h * ax;
-        a.vy[i] = a.vy[i] - a.h * ay;
-        a.vz[i] = a.vz[i] - a.h * az;
+        a.vx[i] = fmat(-a.h, ax, a.vx[i]);
+        a.vy[i] = fmat(-a.h, ay, a.vy[i]);
+        a.vz[i] = fmat(-a.h, az, a.vz[i]);
+    }
+    if (a.rx) {  // the next step's reverse drift, as the reverse-drift kernel does it
+        const double h = a.h, dt = a.dt;
+        a.rlx[i] = fmat(dt, a.gx[i], a.rlx[i]);
+        a.rly[i] = fmat(dt, a.gy[i], a.rly[i]);
+        a.rlz[i] = fmat(dt, a.gz[i], a.rlz[i]);
+        const double vx = fmat(-h, a.ax[i], a.vx[i]), vy = fmat(-h, a.ay[i], a.vy[i]),
+                     vz = fmat(-h, a.az[i], a.vz[i]);
+        a.vx[i] = vx;
+        a.vy[i] = vy;
+        a.vz[i] = vz;
+        a.rx[i] = fmat(-dt, vx, a.rx[i]);
+        a.ry[i] = fmat(-dt, vy, a.ry[i]);
+        a.rz[i] = fmat(-dt, vz, a.rz[i]);
     }
 }
 
@@ -310,7 +327,9 @@ size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n) {
 hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                               const void* lam_v, double eps, double G, double c,
                               bool update_state, double h, void* acc, void* v, void* lam_x,
-                              double* lam_m, void* ws, hipStream_t stream) {
+                              double* lam_m, void* ws, hipStream_t stream, void* drift_x,
+                              double drift_dt, bool* drifted) {
+    if (drifted) *drifted = false;
     const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
     if (bi == 0) return hipErrorInvalidValue;
     ASymArgs a{};
@@ -348,6 +367,14 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     f.vx = pv; f.vy = pv + n; f.vz = pv + 2 * n;
     f.gx = pg; f.gy = pg + n; f.gz = pg + 2 * n;
     f.gm = lam_m;
+    if (drift_x) {  // the finishing kernel runs after every read of x and lam_v
+        double* prx = static_cast<double*>(drift_x);
+        double* prl = static_cast<double*>(const_cast<void*>(lam_v));
+        f.rx = prx; f.ry = prx + n; f.rz = prx + 2 * n;
+        f.rlx = prl; f.rly = prl + n; f.rlz = prl + 2 * n;
+        f.dt = drift_dt;
+    }
+    if (drifted) *drifted = drift_x != nullptr;
     if (update_state)
         hipLaunchKernelGGL(adjoint_sym_finish_kernel<true>, dim3((unsigned)((n + 255) / 256)),
                            dim3(256), 0, stream, f);

@@ -193,10 +193,16 @@ hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void*
 // G^T lam_v and applies the epilogue
 //   lam_x += c J^T lam_v;  lam_m += c G^T lam_v;
 //   if update_state: acc = a(x); v = v - h acc.
+// drift_x (optional): then also the next step's reverse drift,
+//   lam_v += drift_dt lam_x; v -= h acc; x -= drift_dt v,
+// where the pass has a finishing kernel that runs after every read of x and
+// lam_v (*drifted, if given, tells whether it did).
 hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x,
                           const void* m, const void* lam_v, double eps, double G,
                           double c, bool update_state, double h, void* acc, void* v,
-                          void* lam_x, double* lam_m, void* ws, hipStream_t stream);
+                          void* lam_x, double* lam_m, void* ws, hipStream_t stream,
+                          void* drift_x = nullptr, double drift_dt = 0.0,
+                          bool* drifted = nullptr);
 
 // Symmetric form of the fused adjoint pass (NB_MIX_TILEC only), same
 // contract as launch_adjoint; ws holds adjoint_sym_partials_bytes(sh, n).
@@ -205,7 +211,9 @@ size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n);
 hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                               const void* lam_v, double eps, double G, double c,
                               bool update_state, double h, void* acc, void* v, void* lam_x,
-                              double* lam_m, void* ws, hipStream_t stream);
+                              double* lam_m, void* ws, hipStream_t stream,
+                              void* drift_x = nullptr, double drift_dt = 0.0,
+                              bool* drifted = nullptr);
 
 // O(N) leapfrog kernels over the 3n components of a pos array.
 hipError_t launch_kick_drift(int prec, int64_t n, void* x, void* v, const void* acc,

@@ -40,10 +40,10 @@ __global__ __launch_bounds__(TPB) void reverse_drift_kernel(T* __restrict__ x, T
                                                             int64_t count) {
     for (int64_t k = blockIdx.x * (int64_t)TPB + threadIdx.x; k < count;
          k += (int64_t)gridDim.x * TPB) {
-        lv[k] = lv[k] + dt * lx[k];
-        const T vh = v[k] - h * a[k];
+        lv[k] = fmat(dt, lx[k], lv[k]);  // the same FMAs as the adjoint epilogue's
+        const T vh = fmat(-h, a[k], v[k]);
         v[k] = vh;
-        x[k] = x[k] - dt * vh;
+        x[k] = fmat(-dt, vh, x[k]);
     }
 }
 

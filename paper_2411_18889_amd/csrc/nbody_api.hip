@@ -420,19 +420,31 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
     const double h = 0.5 * dt;
     double* lm = static_cast<double*>(lam_m);
     hipError_t e = hipSuccess;
-    auto fused = [&](double c, bool update_state) {
+    // fused(c, update_state, drift): one adjoint pass; with drift its
+    // finishing kernel (where the pass has one) also applies the next step's
+    // reverse drift, and `drifted` records that it did
+    bool drifted = false;
+    auto fused = [&](double c, bool update_state, bool drift) {
+        drifted = false;
         return timed(NB_PROF_ADJOINT, s, [&] {
+            void* dx = drift ? x : nullptr;
             if (sym.waves)
                 return launch_adjoint_sym(sym, n, x, m, lam_v, eps, G, c, update_state, h, acc, v,
-                                          lam_x, lm, ws, s);
+                                          lam_x, lm, ws, s, dx, dt, &drifted);
             return launch_adjoint(prec, sh, n, x, m, lam_v, eps, G, c, update_state, h, acc, v, lam_x,
-                                  lm, ws, s);
+                                  lm, ws, s, dx, dt, &drifted);
         });
     };
-    if (flags & NB_ADJ_ENTRY_HALF) e = fused(h, false);
+    // the state walked back to at loop index k, and whether it is reloaded
+    auto anchor_at = [&](int64_t k) {
+        return k < nsteps && ckpt && ((step_end - 1 - k) % ckpt_every == 0);
+    };
+    if (flags & NB_ADJ_ENTRY_HALF) e = fused(h, false, nsteps > 0 && !anchor_at(0));
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
         const int64_t step = step_end - 1 - k;  // absolute index of the state walked back to
-        const bool anchor = ckpt && (step % ckpt_every == 0);
+        const bool anchor = anchor_at(k);
+        const bool walked = drifted;  // the previous pass already did this step's reverse drift
+        drifted = false;
         if (anchor) {
             e = timed(NB_PROF_UPDATE, s, [&] { return launch_axpy_pos(prec, 3 * n, lam_v, lam_x, dt, s); });
             const char* base = static_cast<const char*>(ckpt) + (size_t)(step / ckpt_every) * 3 * vb;
@@ -443,14 +455,14 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
                     if (r == hipSuccess) r = copy_state(acc, base + 2 * vb, vb, s);
                     return r;
                 });
-        } else {
+        } else if (!walked) {
             e = timed(NB_PROF_UPDATE, s, [&] {
                 return launch_reverse_drift(prec, n, x, v, acc, lam_x, lam_v, h, dt, s);
             });
         }
         const bool last = (k == nsteps - 1);
         const double c = last ? ((flags & NB_ADJ_EXIT_FULL) ? dt : h) : dt;
-        if (e == hipSuccess) e = fused(c, !anchor);
+        if (e == hipSuccess) e = fused(c, !anchor, !last && !anchor_at(k + 1));
     }
     return hip_status(e);
 }

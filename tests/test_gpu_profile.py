@@ -32,9 +32,10 @@ def test_profile_counts_and_times():
     # forward: a(x_0) + S force passes, each with its closing kick and, but
     # for the last, the next step's kick and drift in its finishing kernel
     # (4096 sinks: split source ranges, so the pass has one), so one
-    # separate kick-drift; adjoint: entry pass + S fused passes, S reverse
-    # drifts
-    assert list(prof.calls) == [S + 1, S + 1, 1 + S, 0, 0]
+    # separate kick-drift; adjoint: entry pass + S fused passes, each but the
+    # last with the next step's reverse drift in its finishing kernel, so no
+    # separate reverse drift
+    assert list(prof.calls) == [S + 1, S + 1, 1, 0, 0]
     assert all(prof.ms[k] > 0 for k in range(3))
     # a graph replay is not taken while profiling: the launch groups are
     # timed one by one as in an eager call
