@@ -31,10 +31,65 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FP32_VECTOR_PEAK = 157.3e12      # MI355X published FP32 vector peak (counts packed FP32)
+FP32_VECTOR_PEAK = 157.3e12      # MI355X published FP32 vector peak
 PEAK_CLOCK_MHZ = 2400.0          # the shader clock the published peaks assume
-FLOP_PER_FORCE_PAIR = 20         # 3 sub + 3 FMA + 3 mul + 3 FMA (FMA = 2) + 2 for rsqrt
-FLOP_PER_ADJOINT_PAIR = 55       # count of the fused adjoint pair body, same convention
+
+# The paper's convention: flop per interaction (i, j), counted from the pair
+# body of its listing -- 3 sub + 3 FMA + 3 mul + 3 FMA with FMA = 2, plus 2
+# for the reciprocal square root -- and the same count for the fused adjoint
+# body; N^2 interactions per pass.
+FLOP_PER_INTERACTION_FORCE = 20
+FLOP_PER_INTERACTION_ADJOINT = 55
+
+# Executed flop per pair evaluation, counted from the kernels' pair bodies
+# (FMA = 2, reciprocal square root = 2). A one-sided evaluation serves one
+# sink; an off-diagonal evaluation of the symmetric passes serves both ends
+# of the pair (the diagonal block items evaluate every pair from both ends,
+# one-sided).
+#   force, one-sided: 3 sub, 3 FMA (s), 3 mul (r^3 m_j), 3 FMA (sum) = 20
+#   force, symmetric: + 1 mul (r^3 m_i) + 3 FMA (source side) = 27
+#   adjoint, one-sided with the force sums: 55 (without them: 48)
+#   adjoint, symmetric with the force sums: 73 (without them: 59): the one-
+#     sided body + d.lam_i (5) - 2 for d.u from the two dots + the source
+#     side (1 mul + 7 FMA with the force sums, 4 FMA without)
+EXEC_FLOP = {("force", False): 20, ("force", True): 27,
+             ("adjoint", False, True): 55, ("adjoint", False, False): 48,
+             ("adjoint", True, True): 73, ("adjoint", True, False): 59}
+
+
+def pair_evaluations(n, info):
+    """(off-diagonal, one-sided) pair evaluations of one pass over n
+    particles in the pass `info` (nbody_pass_info): the symmetric passes
+    evaluate each pair of different blocks once and the pairs inside a block
+    from both ends; the one-sided kernel evaluates all n^2."""
+    n = int(n)
+    if not info["symmetric"]:
+        return 0.0, float(n) * n
+    b = int(info["block_particles"])
+    full, tail = divmod(n, b)
+    diag = float(full) * b * b + float(tail) * tail
+    return (float(n) * n - diag) / 2.0, diag
+
+
+def executed_flop(kind, n, info, force_sums=True):
+    """Executed flop of one pass (kind "force" or "adjoint")."""
+    off, one = pair_evaluations(n, info)
+    if kind == "force":
+        return off * EXEC_FLOP[("force", True)] + one * EXEC_FLOP[("force", False)]
+    sym_f = EXEC_FLOP[("adjoint", True, force_sums)]
+    # the one-sided adjoint kernel always carries the force sums; the
+    # diagonal items of the symmetric one only when asked for
+    one_f = EXEC_FLOP[("adjoint", False, force_sums if info["symmetric"] else True)]
+    return off * sym_f + one * one_f
+
+
+def adjoint_schedule(R, K):
+    """(passes with the force sums, passes without) of the reverse walk of an
+    R-step rollout checkpointed every K steps, started with the entry-half
+    update at step R: the entry pass and the passes at reloaded (checkpoint)
+    states need no force sums, every walked-back state does."""
+    anchors = sum(1 for s in range(R) if s % K == 0)
+    return R - anchors, 1 + anchors
 
 
 def parse():
@@ -331,56 +386,60 @@ def main():
 
     f_ms = prof.ms[0] / max(1, prof.calls[0])
     a_ms = prof.ms[1] / max(1, prof.calls[1])
-    force_tflops = FLOP_PER_FORCE_PAIR * float(n) * n / (f_ms * 1e-3) / 1e12
-    adj_tflops = FLOP_PER_ADJOINT_PAIR * float(n) * n / (a_ms * 1e-3) / 1e12
     kinds = ["force", "adjoint", "update", "diag", "copy"]
     per_kind = {k: {"ms_per_step": prof.ms[i] / args.steps, "calls": int(prof.calls[i])}
                 for i, k in enumerate(kinds)}
     fwd_ms = sum(a.elapsed_time(b) for a, b, _, _ in pass_events) / len(pass_events)
     adj_ms = sum(c.elapsed_time(d) for _, _, c, d in pass_events) / len(pass_events)
-    # the passes the library runs here: the symmetric (third-law) kernels
-    # evaluate each pair once for two interactions
+    # the passes the library runs here (the symmetric kernels evaluate each
+    # pair of different blocks once, for both ends)
     fpass, apass = nb.pass_info(1, n, prec), nb.pass_info(2, n, prec)
     fk = "force_sym_kernel" if fpass["symmetric"] else "force_kernel"
     ak = "adjoint_sym_kernel" if apass["symmetric"] else "adjoint_kernel"
-    pairs_per_interaction = 0.5 if fpass["symmetric"] else 1.0
-    dom = "adjoint" if prof.ms[1] >= prof.ms[0] else "force"
-    if dom == "adjoint":
-        roof = {"kernel": ak + " (fused force + J^T lam + G^T lam)", "bound": "alu",
-                "achieved": adj_tflops, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": adj_tflops * 1e12 / FP32_VECTOR_PEAK,
-                "traffic": hbm_traffic(ak, w.name),
-                "pair_evaluations_per_interaction": 0.5 if apass["symmetric"] else 1.0,
-                "shape": apass,
-                "flop_per_pair": FLOP_PER_ADJOINT_PAIR, "avg_launch_ms": a_ms}
-    else:
-        roof = {"kernel": fk, "bound": "alu", "achieved": force_tflops,
-                "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK,
-                "traffic": hbm_traffic(fk, w.name),
-                "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
-    force_roof = {"kernel": fk, "bound": "alu", "achieved": force_tflops,
-                  "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                  "frac": force_tflops * 1e12 / FP32_VECTOR_PEAK,
-                  "traffic": hbm_traffic(fk, w.name),
-                  "ginteractions_per_s": float(n) * n / (f_ms * 1e-3) / 1e9,
-                  "pair_evaluations_per_interaction": pairs_per_interaction,
-                  "shape": fpass,
-                  "flop_per_pair": FLOP_PER_FORCE_PAIR, "avg_launch_ms": f_ms}
+    # executed work per launch: the force pass is the same every time; the
+    # adjoint passes of one walk carry the force sums or not (entry and
+    # reloaded states), averaged over the walk
+    nF, nNoF = adjoint_schedule(R, K)
+    f_flop = executed_flop("force", n, fpass)
+    a_flop = (nF * executed_flop("adjoint", n, apass, True)
+              + nNoF * executed_flop("adjoint", n, apass, False)) / (nF + nNoF)
+    f_off, f_one = pair_evaluations(n, fpass)
+    a_off, a_one = pair_evaluations(n, apass)
+    peak_tf = FP32_VECTOR_PEAK / 1e12
 
-    # what the counted HBM bytes are made of: the symmetric passes write one
-    # FP32 partial per particle, quantity and block (the workspace) and read
-    # it back in the finishing kernel -- the cost of a fixed-order reduction
-    # without atomics; the algorithmic bytes are the state in and out
-    for r, info in ((roof, apass if dom == "adjoint" else fpass), (force_roof, fpass)):
+    def roofline(kernel, info, flop, ms, conv_flop, off, one, what):
+        tf = flop / (ms * 1e-3) / 1e12
+        conv_tf = conv_flop * float(n) * n / (ms * 1e-3) / 1e12
+        r = {"kernel": kernel + what, "bound": "alu", "achieved": tf, "peak": peak_tf,
+             "unit": "TFLOP/s", "frac": tf / peak_tf,
+             "traffic": hbm_traffic(kernel, w.name),
+             "executed_flop_per_launch": flop,
+             "pair_evaluations_per_launch": off + one,
+             "pair_evaluations_both_ends": off, "pair_evaluations_one_sided": one,
+             "shape": info, "avg_launch_ms": ms,
+             "ginteractions_per_s": float(n) * n / (ms * 1e-3) / 1e9,
+             "paper_convention": {"flop_per_interaction": conv_flop,
+                                  "interactions_per_launch": float(n) * n,
+                                  "achieved": conv_tf, "frac": conv_tf / peak_tf}}
         if info["symmetric"] and r["traffic"] is not None:
+            # the FP32 partials per particle, quantity and block that the pass
+            # writes and its finishing kernel reads back: the price of a fixed-
+            # order reduction without atomics
             r["traffic_partials_written"] = info["workspace_bytes"]
-            r["traffic_rate_tb_s"] = r["traffic"] / (r["avg_launch_ms"] * 1e-3) / 1e12
+            r["traffic_rate_tb_s"] = r["traffic"] / (ms * 1e-3) / 1e12
+        return r
+
+    roof_adj = roofline(ak, apass, a_flop, a_ms, FLOP_PER_INTERACTION_ADJOINT, a_off, a_one,
+                        " (fused force + J^T lam + G^T lam)")
+    roof_adj["passes_with_force_sums"], roof_adj["passes_without"] = nF, nNoF
+    force_roof = roofline(fk, fpass, f_flop, f_ms, FLOP_PER_INTERACTION_FORCE, f_off, f_one, "")
+    dom = "adjoint" if prof.ms[1] >= prof.ms[0] else "force"
+    roof = roof_adj if dom == "adjoint" else force_roof
 
     clk = clocks.summary()
     if clk:
         # the same achieved rate against the peak scaled to the measured clock
-        for r in (roof, force_roof):
+        for r in (roof_adj, force_roof):
             r["frac_at_measured_sclk"] = r["frac"] * PEAK_CLOCK_MHZ / clk["sclk_mhz_mean"]
 
     D0 = nb.diag_dict(d0)
@@ -441,7 +500,8 @@ def main():
                    "step": "diag + forward rollout (R+1 force passes) + diag + adjoint walk "
                            "(R+1 fused passes)"},
         "roofline": roof,
-        "force_kernel": force_roof,
+        ("force_kernel" if dom == "adjoint" else "adjoint_kernel"):
+            force_roof if dom == "adjoint" else roof_adj,
         "forward_pass_ms": fwd_ms,
         "adjoint_pass_ms": adj_ms,
         "adjoint_over_forward": adj_ms / fwd_ms,

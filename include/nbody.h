@@ -24,7 +24,8 @@
  *   NB_GRAPH are runtime objects, freed by nbody_graph_cache_clear()).
  *   Scratch memory comes from the caller's workspace `ws` (device memory,
  *   256-byte aligned, at least nbody_workspace_size() bytes; may be NULL
- *   when that size is 0).
+ *   when that size is 0). The part of the workspace a call uses must not
+ *   overlap any other buffer of the call (NB_EINVAL).
  *
  * Pair passes and reproducibility
  *   The pair sums run in one of two forms, chosen by n and the policy
@@ -83,9 +84,13 @@ typedef enum nb_status {
  *                 running sums, as the paper's listing (in the symmetric
  *                 pass, for a set on itself from 12288 particles, FP32 sums
  *                 over each source block, then over the blocks in FP32).
- *   NB_MIX_ACC32  pos double, mass float. Positions are rounded to FP32 for
- *                 the pair arithmetic (FP32, as NB_F32); FP32 running sums.
- *                 Kick, drift and everything O(N) stay in FP64.
+ *   NB_MIX_ACC32  pos double, mass float. Pair arithmetic in FP32 (as
+ *                 NB_F32) on positions taken relative to an origin o, the
+ *                 FP64 centroid of the sinks one workgroup owns (a
+ *                 contiguous index range), and then rounded: the rounding
+ *                 error of a separation is at most 2^-24 (|x_i - o| +
+ *                 |x_j - o|), independent of where the system sits. FP32
+ *                 running sums. Kick, drift and everything O(N) stay in FP64.
  *   NB_MIX_KAHAN  as NB_MIX_ACC32, but each running sum is Kahan-compensated
  *                 in FP32.
  *   NB_MIX_ACC64  as NB_MIX_ACC32, but each FP32 pair term is summed in FP64.

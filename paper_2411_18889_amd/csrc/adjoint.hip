@@ -17,8 +17,8 @@
 // the sum; plus 4 for the mass adjoint and the 12 + rsqrt of the force:
 // 34 VALU + 1 rsqrt.
 //
-// Tiling, j-split and the fixed-order split reduction are as in the force
-// kernel; the LDS record of a source is (x, y, z, m) and (lam_x, lam_y,
+// Tiling, j-split, the origin of the pair arithmetic in the mixed policies
+// and the fixed-order split reduction are as in the force kernel; the LDS record of a source is (x, y, z, m) and (lam_x, lam_y,
 // lam_z, 0).
 #include <algorithm>
 
@@ -98,16 +98,34 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(AdjArgs<Pol> a) {
     __shared__ V4 tl[BS];
 
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * (BS * K) + tid;
+    const int b0 = blockIdx.x * (BS * K);
+    const int i0 = b0 + tid;
+    // origin of the pair arithmetic (mixed policies): the centroid of this
+    // workgroup's sinks
+    double ox = 0.0, oy = 0.0, oz = 0.0;
+    if constexpr (Pol::origin) {
+        __shared__ double org[BS / 64][3];
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k * BS;
+            if (i < a.n) {
+                cx += a.x[i];
+                cy += a.y[i];
+                cz += a.z[i];
+            }
+        }
+        sink_block_origin<BS / 64>(cx, cy, cz, min(a.n - b0, BS * K), org, ox, oy, oz);
+    }
     calc_t xi[K], yi[K], zi[K], mi[K], lxi[K], lyi[K], lzi[K];
     sum_t s[K][NQ];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = i0 + k * BS;
         const bool ok = i < a.n;
-        xi[k] = ok ? calc_t(a.x[i]) : calc_t(0);
-        yi[k] = ok ? calc_t(a.y[i]) : calc_t(0);
-        zi[k] = ok ? calc_t(a.z[i]) : calc_t(0);
+        xi[k] = ok ? pair_coord<Pol>(a.x[i], ox) : calc_t(0);
+        yi[k] = ok ? pair_coord<Pol>(a.y[i], oy) : calc_t(0);
+        zi[k] = ok ? pair_coord<Pol>(a.z[i], oz) : calc_t(0);
         mi[k] = ok ? calc_t(a.m[i]) : calc_t(0);
         lxi[k] = ok ? calc_t(a.lx[i]) : calc_t(0);
         lyi[k] = ok ? calc_t(a.ly[i]) : calc_t(0);
@@ -123,7 +141,10 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(AdjArgs<Pol> a) {
         const int j = jt + tid;
         V4 p, l;
         if (j < jend) {
-            p.x = calc_t(a.x[j]); p.y = calc_t(a.y[j]); p.z = calc_t(a.z[j]); p.w = calc_t(a.m[j]);
+            p.x = pair_coord<Pol>(a.x[j], ox);
+            p.y = pair_coord<Pol>(a.y[j], oy);
+            p.z = pair_coord<Pol>(a.z[j], oz);
+            p.w = calc_t(a.m[j]);
             l.x = calc_t(a.lx[j]); l.y = calc_t(a.ly[j]); l.z = calc_t(a.lz[j]); l.w = calc_t(0);
         } else {  // zero mass and zero adjoint: contributes exactly 0
             p.x = p.y = p.z = p.w = calc_t(0);

@@ -10,9 +10,10 @@
 // pair (d . u comes from the two dot products with lam_i and lam_j, which
 // the mass adjoints need anyway), i.e. 21.5 VALU + 1/2 rsqrt per
 // interaction against 34 + 1 one-sided.
-// The blocking, the work items (block pairs I <= J), the source-side sums
-// carried through the lanes and the fixed-order FP32 partials are those of
-// the symmetric force pass, with seven quantities instead of three:
+// The blocking, the work items (block pairs I <= J), the origin of the pair
+// arithmetic (the centroid of block I), the source-side sums carried through
+// the lanes and the fixed-order FP32 partials are those of the symmetric
+// force pass, with seven quantities instead of three:
 // a (3), J^T lam (3) and the mass-adjoint sum (1). The finishing kernel adds
 // the partials in slot order in FP64 and applies the adjoint epilogue of the
 // reverse walk.
@@ -167,15 +168,32 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int ibase = I * BI + w * 64 * K + lane;
+    // origin of the pair arithmetic: the centroid of block I (see
+    // sink_block_origin), for both ends of every pair of the item
+    __shared__ double org[W][3];
+    double ox, oy, oz;
+    {
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = ibase + k * 64;
+            if (i < a.n) {
+                cx += a.x[i];
+                cy += a.y[i];
+                cz += a.z[i];
+            }
+        }
+        sink_block_origin<W>(cx, cy, cz, min(a.n - I * BI, BI), org, ox, oy, oz);
+    }
     float xi[K], yi[K], zi[K], mi[K], lxi[K], lyi[K], lzi[K];
     SumTile s[K][NQ];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
         const bool ok = i < a.n;
-        xi[k] = ok ? float(a.x[i]) : 0.f;
-        yi[k] = ok ? float(a.y[i]) : 0.f;
-        zi[k] = ok ? float(a.z[i]) : 0.f;
+        xi[k] = ok ? float(a.x[i] - ox) : 0.f;
+        yi[k] = ok ? float(a.y[i] - oy) : 0.f;
+        zi[k] = ok ? float(a.z[i] - oz) : 0.f;
         mi[k] = ok ? a.m[i] : 0.f;  // a padding sink adds exactly 0 to the j side
         lxi[k] = ok ? float(a.lx[i]) : 0.f;
         lyi[k] = ok ? float(a.ly[i]) : 0.f;
@@ -192,7 +210,8 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
             float4 p = make_float4(0.f, 0.f, 0.f, 0.f);  // zero mass and adjoint: adds 0
             float4 l = make_float4(0.f, 0.f, 0.f, 0.f);
             if (j < je) {
-                p = make_float4(float(a.x[j]), float(a.y[j]), float(a.z[j]), a.m[j]);
+                p = make_float4(float(a.x[j] - ox), float(a.y[j] - oy), float(a.z[j] - oz),
+                                a.m[j]);
                 l = make_float4(float(a.lx[j]), float(a.ly[j]), float(a.lz[j]), 0.f);
             }
             rp[q >> 6][q & 63] = p;

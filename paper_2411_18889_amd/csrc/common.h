@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "nbody.h"
 
 namespace nb {
@@ -96,6 +98,64 @@ struct SumTile {
 };
 
 // ---------------------------------------------------------------------------
+// Origin of the FP32 pair arithmetic in the mixed policies.
+//
+// There positions are FP64 and the pair arithmetic FP32. Rounding x itself
+// to FP32 would give the separation d = x_j - x_i an absolute error of up to
+// 2^-24 (|x_i| + |x_j|): relative error 2^-24 |x| / |d|, growing with the
+// distance from the coordinate origin. Instead every workgroup subtracts,
+// in FP64, the centroid o of its own sinks (one contiguous index range)
+// from those sinks and from every source it stages, and rounds x - o: the
+// error of d is then at most 2^-24 (|x_i - o| + |x_j - o|), whatever the
+// position of the system, and the same d serves both ends of a pair in the
+// symmetric passes. The centroid is a fixed-order FP64 reduction (xor
+// butterfly within each wave -- every lane ends with bitwise the same sum --
+// then the wave sums in wave order), so results stay reproducible.
+//
+// s*: this thread's FP64 sum over its valid sinks; count: valid sinks of the
+// workgroup (>= 1); lds: NW x 3 doubles of shared memory. Contains a
+// workgroup barrier: every thread of the workgroup must call it.
+// ---------------------------------------------------------------------------
+// A value that every lane of the wave holds, moved to a scalar register.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+template <int NW>
+__device__ __forceinline__ void sink_block_origin(double sx, double sy, double sz, int count,
+                                                  double (*lds)[3], double& ox, double& oy,
+                                                  double& oz) {
+#pragma unroll
+    for (int mask = 32; mask >= 1; mask >>= 1) {
+        sx += __shfl_xor(sx, mask, 64);
+        sy += __shfl_xor(sy, mask, 64);
+        sz += __shfl_xor(sz, mask, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        lds[w][0] = sx;
+        lds[w][1] = sy;
+        lds[w][2] = sz;
+    }
+    __syncthreads();
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+        tx += lds[v][0];
+        ty += lds[v][1];
+        tz += lds[v][2];
+    }
+    // every lane holds bitwise the same origin: keep it in scalar registers
+    // (the pair loops need every vector register they can get)
+    const double c = double(count);
+    ox = wave_uniform(tx / c);
+    oy = wave_uniform(ty / c);
+    oz = wave_uniform(tz / c);
+}
+
+// ---------------------------------------------------------------------------
 // Precision traits: storage types and the pair-arithmetic type.
 // ---------------------------------------------------------------------------
 template <typename Pos, typename Mass, typename Calc, typename Sum>
@@ -104,7 +164,23 @@ struct Policy {
     using mass_t = Mass;  // masses
     using calc_t = Calc;  // pair arithmetic
     using sum_t = Sum;    // per-sink running sum
+    // FP64 positions, FP32 pair arithmetic: positions are taken relative to
+    // the sink block's centroid before they are rounded (sink_block_origin)
+    static constexpr bool origin =
+        std::is_same<Pos, double>::value && std::is_same<Calc, float>::value;
 };
+
+// A stored coordinate as the pair arithmetic takes it: relative to the
+// origin o in FP64, then rounded, where the policy has an origin; else the
+// coordinate converted as it is (o is then ignored; it is 0).
+template <class Pol>
+__device__ __forceinline__ typename Pol::calc_t pair_coord(typename Pol::pos_t x, double o) {
+    using calc_t = typename Pol::calc_t;
+    if constexpr (Pol::origin)
+        return calc_t(double(x) - o);
+    else
+        return calc_t(x);
+}
 
 using PolF64 = Policy<double, double, double, SumPlain<double>>;
 using PolF32 = Policy<float, float, float, SumPlain<float>>;
@@ -229,6 +305,30 @@ hipError_t launch_axpy_pos(int prec, int64_t n3, void* y, const void* xv, double
 // One step of the 3-D diffusion stencil (FP32 grid, k fastest).
 hipError_t launch_diffusion3d(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, double dz,
                               double dt, double kappa, const float* f, float* fn, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Entry-point plumbing shared by the ABI translation units.
+// ---------------------------------------------------------------------------
+// The pass nbody_accel runs for a call, once its arguments are checked.
+struct AccelPlan {
+    SymShape sym;   // the symmetric pass (sym.waves != 0), or
+    Shape sh;       // the one-sided kernel in this shape
+    bool self_set;
+    size_t need;    // scratch bytes the pass needs
+};
+// Checks the arguments of nbody_accel / nbody_accel_ex (not the workspace)
+// and fills *plan; returns an nb_status.
+int accel_plan(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
+               double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
+               AccelPlan* plan);
+// Enqueues the planned pass with plan.need bytes of scratch at ws.
+hipError_t accel_launch(const AccelPlan& p, int64_t ni, const void* xi, int64_t nj, const void* xj,
+                        const void* mj, double eps, double G, int prec, void* acc, void* pot,
+                        void* ws, hipStream_t s);
+// NB_OK if a gfx950 device is current, else NB_ENODEV.
+int check_device();
+// NB_OK, or NB_EDEVICE after recording the HIP error for nbody_last_hip_error.
+int hip_status(hipError_t e);
 
 // FP64 diagnostics into out[13] (device).
 size_t diag_workspace_bytes(int64_t n);

@@ -6,7 +6,9 @@
 //    loads and stores of a wave are contiguous);
 //  * the sources are streamed in j-tiles of BS particles: every lane loads
 //    one source from the SoA arrays (coalesced), rounds it to the pair
-//    arithmetic type and stores it in LDS as (x, y, z, m); after a barrier
+//    arithmetic type (in the mixed policies relative to the centroid of the
+//    workgroup's sinks, see sink_block_origin) and stores it in LDS as
+//    (x, y, z, m); after a barrier
 //    every lane walks the whole tile, and every LDS read is a broadcast (all
 //    lanes read the same address, so no bank conflicts);
 //  * per pair: 3 subtractions, 3 FMAs for |d|^2 + eps^2 (eps^2 innermost, as
@@ -96,16 +98,34 @@ __global__ __launch_bounds__(BS) void force_kernel(ForceArgs<Pol> a) {
     __shared__ V4 tile[BS];
 
     const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * (BS * K) + tid;
+    const int b0 = blockIdx.x * (BS * K);
+    const int i0 = b0 + tid;
+    // origin of the pair arithmetic (mixed policies): the centroid of this
+    // workgroup's sinks
+    double ox = 0.0, oy = 0.0, oz = 0.0;
+    if constexpr (Pol::origin) {
+        __shared__ double org[BS / 64][3];
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k * BS;
+            if (i < a.ni) {
+                cx += a.xi[i];
+                cy += a.yi[i];
+                cz += a.zi[i];
+            }
+        }
+        sink_block_origin<BS / 64>(cx, cy, cz, min(a.ni - b0, BS * K), org, ox, oy, oz);
+    }
     calc_t xi[K], yi[K], zi[K];
     sum_t sx[K], sy[K], sz[K], sp[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = i0 + k * BS;
         const bool ok = i < a.ni;
-        xi[k] = ok ? calc_t(a.xi[i]) : calc_t(0);
-        yi[k] = ok ? calc_t(a.yi[i]) : calc_t(0);
-        zi[k] = ok ? calc_t(a.zi[i]) : calc_t(0);
+        xi[k] = ok ? pair_coord<Pol>(a.xi[i], ox) : calc_t(0);
+        yi[k] = ok ? pair_coord<Pol>(a.yi[i], oy) : calc_t(0);
+        zi[k] = ok ? pair_coord<Pol>(a.zi[i], oz) : calc_t(0);
         sx[k].init(); sy[k].init(); sz[k].init(); sp[k].init();
     }
     const calc_t eps2 = a.eps2;
@@ -116,9 +136,9 @@ __global__ __launch_bounds__(BS) void force_kernel(ForceArgs<Pol> a) {
         const int j = jt + tid;
         V4 p;
         if (j < jend) {
-            p.x = calc_t(a.xj[j]);
-            p.y = calc_t(a.yj[j]);
-            p.z = calc_t(a.zj[j]);
+            p.x = pair_coord<Pol>(a.xj[j], ox);
+            p.y = pair_coord<Pol>(a.yj[j], oy);
+            p.z = pair_coord<Pol>(a.zj[j], oz);
             p.w = calc_t(a.mj[j]);
         } else {  // zero-mass padding: contributes exactly 0
             p.x = calc_t(0); p.y = calc_t(0); p.z = calc_t(0); p.w = calc_t(0);

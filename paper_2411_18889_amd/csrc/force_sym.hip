@@ -35,7 +35,8 @@
 //    the j = i term m_i / eps, which the finish kernel removes with the same
 //    product the pair loop formed.
 //  * three policies use it: the tile-compensated one (FP64 state, FP32 pair
-//    arithmetic; each group's FP32 i-side sum folded into FP64; FP32
+//    arithmetic on positions taken relative to the centroid of block I, see
+//    sink_block_origin; each group's FP32 i-side sum folded into FP64; FP32
 //    partials added in FP64), plain FP32 (FP32 state; the i-side a running
 //    FP32 sum over the whole source block; the slots added in FP32: every
 //    sum stays FP32, as the policy asks, only blocked by the third-law
@@ -60,6 +61,9 @@ struct SymPol {
     using calc_t = Calc;
     using sum_t = Sum;
     using fin_t = Fin;
+    // FP64 state, FP32 pairs: positions relative to the sink block's centroid
+    static constexpr bool origin =
+        std::is_same<Pos, double>::value && std::is_same<Calc, float>::value;
 };
 using SymTileC = SymPol<double, float, float, SumTile, double>;
 using SymF32 = SymPol<float, float, float, SumPlain<float>, float>;
@@ -191,15 +195,32 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
     const int lane = tid & 63;
     const int w = tid >> 6;
     const int ibase = I * BI + w * 64 * K + lane;
+    // origin of the pair arithmetic (tile-compensated policy): the centroid
+    // of block I, for both ends of every pair of the item
+    double ox = 0.0, oy = 0.0, oz = 0.0;
+    if constexpr (Pol::origin) {
+        __shared__ double org[W][3];
+        double cx = 0.0, cy = 0.0, cz = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = ibase + k * 64;
+            if (i < a.n) {
+                cx += a.x[i];
+                cy += a.y[i];
+                cz += a.z[i];
+            }
+        }
+        sink_block_origin<W>(cx, cy, cz, min(a.n - I * BI, BI), org, ox, oy, oz);
+    }
     C xi[K], yi[K], zi[K], mi[K];
     typename Pol::sum_t s[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
         const bool ok = i < a.n;
-        xi[k] = ok ? C(a.x[i]) : C(0);
-        yi[k] = ok ? C(a.y[i]) : C(0);
-        zi[k] = ok ? C(a.z[i]) : C(0);
+        xi[k] = ok ? pair_coord<Pol>(a.x[i], ox) : C(0);
+        yi[k] = ok ? pair_coord<Pol>(a.y[i], oy) : C(0);
+        zi[k] = ok ? pair_coord<Pol>(a.z[i], oz) : C(0);
         mi[k] = ok ? C(a.m[i]) : C(0);  // a padding sink adds exactly 0 to the j side
         s[k][0].init();
         s[k][1].init();
@@ -213,9 +234,9 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
         for (int q = tid; q < TJ; q += NT) {
             const int j = jt + q;
             V4 p;  // zero-mass padding past the end
-            p.x = j < je ? C(a.x[j]) : C(0);
-            p.y = j < je ? C(a.y[j]) : C(0);
-            p.z = j < je ? C(a.z[j]) : C(0);
+            p.x = j < je ? pair_coord<Pol>(a.x[j], ox) : C(0);
+            p.y = j < je ? pair_coord<Pol>(a.y[j], oy) : C(0);
+            p.z = j < je ? pair_coord<Pol>(a.z[j], oz) : C(0);
             p.w = j < je ? C(a.m[j]) : C(0);
             rec[q >> 6][q & 63] = p;
             rec[q >> 6][(q & 63) + 64] = p;

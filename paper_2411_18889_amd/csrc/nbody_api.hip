@@ -72,6 +72,10 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     return pa < pb + nb && pb < pa + na;
 }
 
+}  // namespace
+
+namespace nb {
+
 // A gfx950 device must be current. The answer is cached per device id.
 int check_device() {
     static std::atomic<int> cache[64];  // 0 unknown, 1 ok, 2 not gfx950
@@ -98,6 +102,10 @@ int hip_status(hipError_t e) {
     g_last_hip_error = (int)e;
     return NB_EDEVICE;
 }
+
+}  // namespace nb
+
+namespace {
 
 int check_ws(void* ws, size_t ws_bytes, size_t need) {
     if (need == 0) return NB_OK;
@@ -206,9 +214,13 @@ hipError_t graph_launch(const StepKey& key, hipStream_t s, F&& enqueue) {
     return e;
 }
 
-int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
-                 double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
-                 void* ws, size_t ws_bytes, void* stream) {
+}  // namespace
+
+namespace nb {
+
+int accel_plan(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
+               double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
+               AccelPlan* plan) {
     if (!valid_prec(prec)) return NB_EUNSUPPORTED;
     if (ni < 1 || nj < 1 || ni > kMaxN || nj > kMaxN) return NB_EINVAL;
     if (!valid_eps(eps, prec) || !isfinite(G)) return NB_EINVAL;
@@ -225,12 +237,12 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
         return NB_EINVAL;
     if (pot && (overlaps(pot, (size_t)ni * ps, acc, acc_b) ||
                 overlaps(pot, (size_t)ni * ps, xi, 3 * (size_t)ni * ps) ||
-                overlaps(pot, (size_t)ni * ps, xj, 3 * (size_t)nj * ps)))
+                overlaps(pot, (size_t)ni * ps, xj, 3 * (size_t)nj * ps) ||
+                overlaps(pot, (size_t)ni * ps, mj, (size_t)nj * ms)))
         return NB_EINVAL;
     // one set on itself, library shape: the symmetric pass where the policy
     // has one
-    const SymShape sym =
-        (self_set && !launch) ? choose_sym_shape(prec, ni, pot != nullptr) : SymShape{0, 0};
+    plan->sym = (self_set && !launch) ? choose_sym_shape(prec, ni, pot != nullptr) : SymShape{0, 0};
     Shape sh = choose_force_shape(prec, ni, nj);
     if (launch) {
         if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
@@ -238,15 +250,56 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
         if (launch->split) sh.split = launch->split;
         if (!shape_supported(sh)) return NB_EUNSUPPORTED;
     }
-    int st = check_ws(ws, ws_bytes,
-                      sym.waves ? sym_partials_bytes(prec, sym, ni, pot != nullptr) : accel_ws(sh, ni));
+    plan->sh = sh;
+    plan->self_set = self_set;
+    plan->need = plan->sym.waves ? sym_partials_bytes(prec, plan->sym, ni, pot != nullptr)
+                                 : accel_ws(sh, ni);
+    return NB_OK;
+}
+
+}  // namespace nb
+
+namespace {
+
+// The scratch must not overlap any buffer of the call.
+bool accel_ws_overlaps(const void* ws, size_t need, int64_t ni, const void* xi, int64_t nj,
+                       const void* xj, const void* mj, int prec, const void* acc, const void* pot) {
+    if (need == 0) return false;
+    const size_t ps = pos_size(prec), ms = mass_size(prec);
+    return overlaps(ws, need, xi, 3 * (size_t)ni * ps) || overlaps(ws, need, xj, 3 * (size_t)nj * ps) ||
+           overlaps(ws, need, mj, (size_t)nj * ms) || overlaps(ws, need, acc, 3 * (size_t)ni * ps) ||
+           overlaps(ws, need, pot, (size_t)ni * ps);
+}
+
+}  // namespace
+
+namespace nb {
+
+hipError_t accel_launch(const AccelPlan& p, int64_t ni, const void* xi, int64_t nj, const void* xj,
+                        const void* mj, double eps, double G, int prec, void* acc, void* pot,
+                        void* ws, hipStream_t s) {
+    return timed(NB_PROF_FORCE, s, [&] {
+        if (p.sym.waves)
+            return launch_force_sym(prec, p.sym, ni, xi, mj, eps, G, acc, ws, s, nullptr, 0.0, pot);
+        return launch_force(prec, p.sh, ni, xi, nj, xj, mj, eps, G, p.self_set, acc, pot, ws, s);
+    });
+}
+
+}  // namespace nb
+
+namespace {
+
+int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
+                 double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
+                 void* ws, size_t ws_bytes, void* stream) {
+    AccelPlan plan;
+    int st = accel_plan(ni, xi, nj, xj, mj, eps, G, prec, acc, pot, launch, &plan);
     if (st != NB_OK) return st;
+    if ((st = check_ws(ws, ws_bytes, plan.need)) != NB_OK) return st;
+    if (accel_ws_overlaps(ws, plan.need, ni, xi, nj, xj, mj, prec, acc, pot)) return NB_EINVAL;
     if ((st = check_device()) != NB_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    return hip_status(timed(NB_PROF_FORCE, s, [&] {
-        if (sym.waves) return launch_force_sym(prec, sym, ni, xi, mj, eps, G, acc, ws, s, nullptr, 0.0, pot);
-        return launch_force(prec, sh, ni, xi, nj, xj, mj, eps, G, self_set, acc, pot, ws, s);
-    }));
+    return hip_status(accel_launch(plan, ni, xi, nj, xj, mj, eps, G, prec, acc, pot, ws,
+                                   static_cast<hipStream_t>(stream)));
 }
 
 }  // namespace
@@ -287,8 +340,13 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
     }
     const Shape sh = choose_force_shape(prec, n, n);
     const SymShape sym = choose_sym_shape(prec, n);
-    int st = check_ws(ws, ws_bytes, sym.waves ? sym_partials_bytes(prec, sym, n) : accel_ws(sh, n));
+    const size_t need = sym.waves ? sym_partials_bytes(prec, sym, n) : accel_ws(sh, n);
+    int st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
+    if (need && (overlaps(ws, need, x, vb) || overlaps(ws, need, v, vb) ||
+                 overlaps(ws, need, m, (size_t)n * ms) || overlaps(ws, need, acc, vb) ||
+                 (ckpt && overlaps(ws, need, ckpt, (size_t)(nsteps / ckpt_every + 1) * 3 * vb))))
+        return NB_EINVAL;
     if ((st = check_device()) != NB_OK) return st;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -414,6 +472,13 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
                                   : (sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0);
     int st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
+    if (need) {
+        if (overlaps(ws, need, m, (size_t)n * ms)) return NB_EINVAL;
+        for (int p = 0; p < 6; ++p)
+            if (overlaps(ws, need, bufs[p], sizes[p])) return NB_EINVAL;
+        if (ckpt && overlaps(ws, need, ckpt, (size_t)(step_end / ckpt_every + 1) * 3 * vb))
+            return NB_EINVAL;
+    }
     if ((st = check_device()) != NB_OK) return st;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -475,8 +540,12 @@ int nbody_diag(int64_t n, const void* x, const void* v, const void* m, double ep
     const size_t ps = pos_size(prec), ms = mass_size(prec);
     if (!x || !v || !m || !out) return NB_EINVAL;
     if (!aligned(x, ps) || !aligned(v, ps) || !aligned(m, ms) || !aligned(out, 8)) return NB_EINVAL;
-    int st = check_ws(ws, ws_bytes, diag_workspace_bytes(n));
+    const size_t need = diag_workspace_bytes(n);
+    int st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
+    if (need && (overlaps(ws, need, x, 3 * (size_t)n * ps) || overlaps(ws, need, v, 3 * (size_t)n * ps) ||
+                 overlaps(ws, need, m, (size_t)n * ms) || overlaps(ws, need, out, 13 * sizeof(double))))
+        return NB_EINVAL;
     if ((st = check_device()) != NB_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     return hip_status(timed(NB_PROF_DIAG, s, [&] { return launch_diag(prec, n, x, v, m, eps, G, out, ws, s); }));

@@ -37,12 +37,28 @@ def per_particle(a, b):
     return float(np.median(e)), float(np.quantile(e, 0.99)), float(e.max())
 
 
-def sample_indices(x, count, central, seed):
+def sample_indices(x, count, central, seed, centres=()):
     """`count` seeded random particles plus the `central` ones nearest the
-    centre of mass (where |a| is smallest and the relative error largest)."""
+    centre of mass (where |a| is smallest and the relative error largest)
+    and the `central` ones nearest each extra point of `centres` (a cluster
+    core, where close pairs are densest)."""
     n = x.shape[1]
     rng = np.random.default_rng(seed)
     idx = rng.choice(n, size=min(count, n), replace=False)
-    r = np.linalg.norm(x - x.mean(axis=1, keepdims=True), axis=0)
-    cen = np.argsort(r)[:central]
-    return np.unique(np.concatenate([idx, cen]))
+    parts = [idx]
+    for c in [x.mean(axis=1)] + [np.asarray(c, dtype=np.float64) for c in centres]:
+        r = np.linalg.norm(x - c[:, None], axis=0)
+        parts.append(np.argsort(r)[:central])
+    return np.unique(np.concatenate(parts))
+
+
+def cluster_centres(name, x):
+    """Cluster cores of a workload beyond its centre of mass: for the
+    subcluster workload, the centroid of the subcluster (its particles come
+    last, round(n / 10) of them)."""
+    from nbody_inputs import WORKLOADS
+    if not WORKLOADS[name].sub_seed:
+        return ()
+    n = x.shape[1]
+    n_sub = int(round(0.1 * n))
+    return (x[:, n - n_sub:].mean(axis=1),)

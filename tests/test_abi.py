@@ -304,3 +304,39 @@ def test_plain_c_consumer(Lv, tmp_path):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout, r.stderr)
+
+
+def test_workspace_overlap_rejected(L):
+    """A workspace that overlaps any buffer of the call is rejected
+    (NB_EINVAL) before any HIP call, as is a potential overlapping the
+    masses: the kernels would race on them. These calls stop in the
+    validation, so they run with or without a GPU."""
+    MiB = 1 << 20
+    xi, xj, mj, acc, pot, ws = (P(k * 64 * MiB) for k in range(1, 7))
+    args = dict(ni=4096, nj=4096, xi=xi, xj=xj, mj=mj, acc=acc, prec=TILEC)
+    need = 16 * 4 * 4096 * 8  # 16 source ranges x 4 FP64 partials per sink
+    for target in (xi, xj, mj, acc):
+        assert _accel(L, ws=P(target.value - 256), wsb=need, **args) == NB_EINVAL
+    assert _accel(L, pot=pot, ws=P(pot.value - 256), wsb=need, **args) == NB_EINVAL
+    assert _accel(L, pot=P(mj.value + 64), **args) == NB_EINVAL  # potential over the masses
+    # the symmetric pass of a set on itself: partials per block
+    n = 20000
+    wsn = L.nbody_workspace_size(1, n, TILEC)
+    x, v, m, a = (P(k * 64 * MiB) for k in range(1, 5))
+    for target in (x, v, m, a):
+        st = L.nbody_step(n, x, v, m, a, 0.01, 1.0, 0.01, 1, TILEC, 0, None, 0,
+                          P(target.value - 256), wsn, None)
+        assert st == NB_EINVAL
+    ck = P(5 * 64 * MiB)
+    st = L.nbody_step(n, x, v, m, a, 0.01, 1.0, 0.01, 2, TILEC, 0, ck, 1, P(ck.value + 256), wsn, None)
+    assert st == NB_EINVAL
+    wsa = L.nbody_workspace_size(2, n, TILEC)
+    lx, lv, lm = (P(k * 64 * MiB) for k in range(6, 9))
+    for target in (x, lx, lv, lm):
+        st = L.nbody_step_adjoint(n, x, v, m, a, lx, lv, lm, 0.01, 1.0, 0.01, 1, TILEC, 0, None, 0,
+                                  0, P(target.value - 256), wsa, None)
+        assert st == NB_EINVAL
+    wsd = L.nbody_workspace_size(3, n, TILEC)
+    out = P(9 * 64 * MiB)
+    assert L.nbody_diag(n, x, v, m, 0.01, 1.0, TILEC, out, P(out.value - 256), wsd, None) == NB_EINVAL
+    assert L.nbody_diag(n, x, v, m, 0.01, 1.0, TILEC, out, P(v.value + 256), wsd, None) == NB_EINVAL
