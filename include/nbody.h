@@ -163,6 +163,31 @@ int nbody_accel(int64_t ni, const void *xi, int64_t nj, const void *xj,
                 void *pot, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * nbody_accel_noalloc -- nbody_accel for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): no workspace argument and no allocation by the library.
+ * The pass, its kernels and its results are those of nbody_accel for the same
+ * arguments (bitwise); its scratch is a device array of the library of
+ * NB_NOALLOC_SCRATCH_BYTES (128 MiB), one per device, held from the library's
+ * first use on that device until the process ends. Arguments and errors as
+ * nbody_accel, plus NB_EWORKSPACE when the pass needs more scratch than that:
+ * the symmetric pass of a set on itself needs nbody_pass_info's
+ * workspace_bytes (NB_OP_STEP; with the potential four partials instead of
+ * three), which fits up to 106,522 particles with the FP32 and
+ * tile-compensated policies and 75,573 with FP64 (without the potential);
+ * separate sets, and sets below 12288 particles, need 4 x 8 x split x ni
+ * bytes for the library's source split (none for large ni). Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (on different streams, or from different threads) race on it and
+ * must be ordered by the caller. Nothing in the array needs clearing
+ * between calls.
+ */
+#define NB_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int nbody_accel_noalloc(int64_t ni, const void *xi, int64_t nj, const void *xj,
+                        const void *mj, double eps, double G, int prec, void *acc,
+                        void *pot, void *stream);
+
+/*
  * nbody_accel_ex -- nbody_accel with an explicit launch shape (for tuning and
  * for tests that a result does not depend on the shape). NULL launch = the
  * library's choice. NB_EUNSUPPORTED for a shape outside nb_launch's limits.

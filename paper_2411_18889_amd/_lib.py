@@ -58,6 +58,7 @@ def lib():
     i64, vp, dbl, i32, sz, u32 = (ctypes.c_int64, ctypes.c_void_p, ctypes.c_double,
                                   ctypes.c_int, ctypes.c_size_t, ctypes.c_uint)
     L.nbody_accel.argtypes = [i64, vp, i64, vp, vp, dbl, dbl, i32, vp, vp, vp, sz, vp]
+    L.nbody_accel_noalloc.argtypes = [i64, vp, i64, vp, vp, dbl, dbl, i32, vp, vp, vp]
     L.nbody_accel_ex.argtypes = [i64, vp, i64, vp, vp, dbl, dbl, i32, vp, vp,
                                  ctypes.POINTER(nb_launch), vp, sz, vp]
     L.nbody_step.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, i64, i32, u32, vp, i64,
@@ -77,7 +78,7 @@ def lib():
     L.nbody_profile_end.argtypes = [ctypes.POINTER(nb_profile_t)]
     L.nbody_graph_cache_clear.argtypes = []
     L.nbody_pass_info.argtypes = [i32, i64, i32, ctypes.POINTER(nb_pass_info)]
-    for f in ("nbody_accel", "nbody_accel_ex", "nbody_step", "nbody_step_adjoint",
+    for f in ("nbody_accel", "nbody_accel_noalloc", "nbody_accel_ex", "nbody_step", "nbody_step_adjoint",
               "nbody_diag", "nbody_last_hip_error", "nbody_device_info",
               "nbody_profile_begin", "nbody_profile_end", "nbody_graph_cache_clear",
               "nbody_pass_info"):

@@ -19,7 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = ["force.hip", "force_sym.hip", "adjoint.hip", "adjoint_sym.hip", "integrate.hip", "diag.hip", "diffusion.hip", "nbody_api.hip"]
+SOURCES = ["force.hip", "force_sym.hip", "adjoint.hip", "adjoint_sym.hip", "integrate.hip", "diag.hip", "diffusion.hip", "nbody_api.hip",
+           "noalloc.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
