@@ -407,7 +407,7 @@ def main():
     a_off, a_one = pair_evaluations(n, apass)
     peak_tf = FP32_VECTOR_PEAK / 1e12
 
-    def roofline(kernel, info, flop, ms, conv_flop, off, one, what):
+    def roofline(kernel, info, flop, ms, conv_flop, off, one, what, partials=0.0):
         tf = flop / (ms * 1e-3) / 1e12
         conv_tf = conv_flop * float(n) * n / (ms * 1e-3) / 1e12
         r = {"kernel": kernel + what, "bound": "alu", "achieved": tf, "peak": peak_tf,
@@ -421,18 +421,28 @@ def main():
              "paper_convention": {"flop_per_interaction": conv_flop,
                                   "interactions_per_launch": float(n) * n,
                                   "achieved": conv_tf, "frac": conv_tf / peak_tf}}
-        if info["symmetric"] and r["traffic"] is not None:
+        if info["symmetric"]:
             # the FP32 partials per particle, quantity and block that the pass
-            # writes and its finishing kernel reads back: the price of a fixed-
-            # order reduction without atomics
-            r["traffic_partials_written"] = info["workspace_bytes"]
-            r["traffic_rate_tb_s"] = r["traffic"] / (ms * 1e-3) / 1e12
+            # writes and its fold kernels read back: the price of a fixed-
+            # order reduction without atomics (the workspace holds one band
+            # of them at a time)
+            r["partials_bytes_per_launch"] = partials
+            if r["traffic"] is not None:
+                r["traffic_rate_tb_s"] = r["traffic"] / (ms * 1e-3) / 1e12
         return r
 
+    def partials(info, nq):  # FP32 partials of one symmetric pass
+        if not info["symmetric"]:
+            return 0.0
+        b = int(info["block_particles"])
+        return float((n + b - 1) // b) * nq * n * 4
+
     roof_adj = roofline(ak, apass, a_flop, a_ms, FLOP_PER_INTERACTION_ADJOINT, a_off, a_one,
-                        " (fused force + J^T lam + G^T lam)")
+                        " (fused force + J^T lam + G^T lam)",
+                        (nF * partials(apass, 7) + nNoF * partials(apass, 4)) / (nF + nNoF))
     roof_adj["passes_with_force_sums"], roof_adj["passes_without"] = nF, nNoF
-    force_roof = roofline(fk, fpass, f_flop, f_ms, FLOP_PER_INTERACTION_FORCE, f_off, f_one, "")
+    force_roof = roofline(fk, fpass, f_flop, f_ms, FLOP_PER_INTERACTION_FORCE, f_off, f_one, "",
+                          partials(fpass, 3))
     dom = "adjoint" if prof.ms[1] >= prof.ms[0] else "force"
     roof = roof_adj if dom == "adjoint" else force_roof
 

@@ -171,12 +171,12 @@ int nbody_accel(int64_t ni, const void *xi, int64_t nj, const void *xj,
  * NB_NOALLOC_SCRATCH_BYTES (128 MiB), one per device, held from the library's
  * first use on that device until the process ends. Arguments and errors as
  * nbody_accel, plus NB_EWORKSPACE when the pass needs more scratch than that:
- * the symmetric pass of a set on itself needs nbody_pass_info's
- * workspace_bytes (NB_OP_STEP; with the potential four partials instead of
- * three), which fits up to 106,522 particles with the FP32 and
- * tile-compensated policies and 75,573 with FP64 (without the potential);
- * separate sets, and sets below 12288 particles, need 4 x 8 x split x ni
- * bytes for the library's source split (none for large ni). Every call on a
+ * the symmetric pass of a set on itself runs in bands within the array (see
+ * nbody_workspace_size) and needs the running sums and one block row, which
+ * fit up to about 2.8 million particles with the tile-compensated policy (2.1
+ * million with the potential), 3.7 million with FP32 and 1.9 million with
+ * FP64; separate sets, and sets below 12288 particles, need 4 x 8 x split x
+ * ni bytes for the library's source split (none for large ni). Every call on a
  * device shares that device's array: calls that overlap in time on one
  * device (on different streams, or from different threads) race on it and
  * must be ordered by the caller. Nothing in the array needs clearing
@@ -301,12 +301,28 @@ typedef struct nb_profile {
 int nbody_profile_begin(void);
 int nbody_profile_end(nb_profile *out);
 
-/* Workspace bytes an operation needs for n particles (0 = none). For
+/* Workspace bytes an operation asks for, for n particles (0 = none). For
  * NB_OP_ACCEL pass max(ni, nj): the size covers every call whose ni and nj
  * are both <= n (a small sink set against many sources takes the most
  * source ranges: up to 512 MiB of partials from n = 2^19 on). Returns 0 for
- * an invalid op or prec. */
+ * an invalid op or prec.
+ * The symmetric passes take less as well: with a workspace that holds every
+ * partial of the pass at once they run as one launch group; with less, in
+ * bands of block rows, each followed by a kernel that adds the band's
+ * partials to running sums per particle (kept at the start of the
+ * workspace) in the same order -- bitwise the same results, at the cost of
+ * more launches. The size asked for holds every partial up to 4 GiB of them,
+ * else the running sums and 4 GiB (or one block row, if more) per band; a
+ * call rejects a workspace that cannot hold the running sums and one block
+ * row (NB_EWORKSPACE), and uses no more than every partial at once. */
 size_t nbody_workspace_size(int op, int64_t n, int prec);
+
+/* The workspace bytes one nbody_accel call (launch == NULL) or
+ * nbody_accel_ex call (launch != NULL) asks for: ni sinks, nj sources,
+ * self_set nonzero when xi == xj (then ni == nj), potential nonzero when pot
+ * is given. 0 when none is needed or the arguments are invalid. */
+size_t nbody_accel_workspace_size(int64_t ni, int64_t nj, int prec, int self_set, int potential,
+                                  const nb_launch *launch);
 
 /*
  * nbody_pass_info -- the pair pass the library runs for n particles acting

@@ -68,6 +68,8 @@ def lib():
     L.nbody_diag.argtypes = [i64, vp, vp, vp, dbl, dbl, i32, vp, vp, sz, vp]
     L.nbody_workspace_size.argtypes = [i32, i64, i32]
     L.nbody_workspace_size.restype = sz
+    L.nbody_accel_workspace_size.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(nb_launch)]
+    L.nbody_accel_workspace_size.restype = sz
     L.nbody_strerror.argtypes = [i32]
     L.nbody_strerror.restype = ctypes.c_char_p
     L.nbody_last_hip_error.argtypes = []

@@ -62,11 +62,19 @@ def _workspace(op, n, prec, device):
     return ws, ctypes.c_void_p(ws.data_ptr()), nbytes
 
 
+def _user_workspace(workspace):
+    if workspace.dtype != torch.uint8 or not workspace.is_contiguous() or workspace.device.type != "cuda":
+        raise ValueError("workspace: contiguous uint8 CUDA tensor")
+    return ctypes.c_void_p(workspace.data_ptr() if workspace.numel() else 0), workspace.numel()
+
+
 def accel(x, m, eps, G=1.0, prec="mix_tilec", xj=None, potential=False, launch=None,
-          out=None, stream=None):
+          out=None, stream=None, workspace=None):
     """a (3, ni) of the sinks x (3, ni) from the sources xj (3, nj) with masses m
     (nj,) -- Eq. (1). xj=None: the set x acts on itself. potential=True also
-    returns phi (ni,)."""
+    returns phi (ni,). workspace: optional uint8 device tensor (the library
+    checks that it is large enough); by default one of the size the library
+    asks for is allocated."""
     p = _prec(prec)
     pdt, mdt = pos_dtype(prec), mass_dtype(prec)
     ni = x.shape[1]
@@ -79,18 +87,21 @@ def accel(x, m, eps, G=1.0, prec="mix_tilec", xj=None, potential=False, launch=N
     pa = _vec(acc, "out", ni, pdt)
     pot = torch.empty(ni, dtype=pdt, device=x.device) if potential else None
     pp = _vec(pot, "pot", ni, pdt, rows=0) if potential else ctypes.c_void_p(0)
-    ws, pws, nws = _workspace(_lib.NB_OP_ACCEL, max(ni, nj), prec, x.device)
     L = _lib.lib()
-    if launch is None:
+    ln = None
+    if launch is not None:
+        ln = nb_launch(*[int(launch.get(k, 0)) for k in ("i_per_lane", "block", "split")])
+    if workspace is not None:
+        pws, nws = _user_workspace(workspace)
+    else:
+        nws = int(L.nbody_accel_workspace_size(ni, nj, p, int(xj is None), int(bool(potential)),
+                                               None if ln is None else ctypes.byref(ln)))
+        ws = torch.empty(nws, dtype=torch.uint8, device=x.device) if nws else None
+        pws = ctypes.c_void_p(ws.data_ptr() if nws else 0)
+    if ln is None:
         st = L.nbody_accel(ni, px, nj, pj, pm, float(eps), float(G), p, pa, pp, pws, nws,
                            _stream(stream))
     else:
-        ln = nb_launch(*[int(launch.get(k, 0)) for k in ("i_per_lane", "block", "split")])
-        if ln.split > 1:  # FP64 partials: split x 4 quantities x ni sinks
-            need = ln.split * 4 * ni * 8
-            if need > nws:
-                ws = torch.empty(need, dtype=torch.uint8, device=x.device)
-                pws, nws = ctypes.c_void_p(ws.data_ptr()), need
         st = L.nbody_accel_ex(ni, px, nj, pj, pm, float(eps), float(G), p, pa, pp,
                               ctypes.byref(ln), pws, nws, _stream(stream))
     check(st, "nbody_accel")
@@ -116,10 +127,7 @@ def step(x, v, m, acc, eps, dt, nsteps, G=1.0, prec="mix_tilec", acc_valid=False
     else:
         pc = ctypes.c_void_p(0)
     if workspace is not None:
-        need = workspace_size(_lib.NB_OP_STEP, n, prec)
-        if workspace.dtype != torch.uint8 or not workspace.is_contiguous() or workspace.numel() < need:
-            raise ValueError("workspace: contiguous uint8 tensor of >= %d bytes" % need)
-        pws, nws = ctypes.c_void_p(workspace.data_ptr() if need else 0), workspace.numel()
+        pws, nws = _user_workspace(workspace)
     else:
         ws, pws, nws = _workspace(_lib.NB_OP_STEP, n, prec, x.device)
     flags = (_lib.NB_ACC_VALID if acc_valid else 0) | (_lib.NB_GRAPH if graph else 0)
@@ -130,9 +138,10 @@ def step(x, v, m, acc, eps, dt, nsteps, G=1.0, prec="mix_tilec", acc_valid=False
 
 def step_adjoint(x, v, m, acc, lam_x, lam_v, lam_m, eps, dt, nsteps, G=1.0,
                  prec="mix_tilec", entry_half=False, exit_full=False, ckpt=None,
-                 ckpt_every=0, step_end=0, stream=None):
+                 ckpt_every=0, step_end=0, stream=None, workspace=None):
     """Walk nsteps KDK steps back from (x, v, acc), updating the adjoints
-    lam_x, lam_v (3, n) and lam_m (n, float64) in place."""
+    lam_x, lam_v (3, n) and lam_m (n, float64) in place. workspace: as
+    accel."""
     p = _prec(prec)
     pdt, mdt = pos_dtype(prec), mass_dtype(prec)
     n = x.shape[1]
@@ -145,7 +154,10 @@ def step_adjoint(x, v, m, acc, lam_x, lam_v, lam_m, eps, dt, nsteps, G=1.0,
     else:
         pc = ctypes.c_void_p(0)
     flags = (_lib.NB_ADJ_ENTRY_HALF if entry_half else 0) | (_lib.NB_ADJ_EXIT_FULL if exit_full else 0)
-    ws, pws, nws = _workspace(_lib.NB_OP_ADJOINT, n, prec, x.device)
+    if workspace is not None:
+        pws, nws = _user_workspace(workspace)
+    else:
+        ws, pws, nws = _workspace(_lib.NB_OP_ADJOINT, n, prec, x.device)
     st = _lib.lib().nbody_step_adjoint(n, *args, float(eps), float(G), float(dt), int(nsteps),
                                        p, flags, pc, int(ckpt_every), int(step_end), pws, nws,
                                        _stream(stream))

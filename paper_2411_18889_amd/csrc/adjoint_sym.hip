@@ -14,9 +14,10 @@
 // arithmetic (the centroid of block I), the source-side sums carried through
 // the lanes and the fixed-order FP32 partials are those of the symmetric
 // force pass, with seven quantities instead of three:
-// a (3), J^T lam (3) and the mass-adjoint sum (1). The finishing kernel adds
-// the partials in slot order in FP64 and applies the adjoint epilogue of the
-// reverse walk.
+// a (3), J^T lam (3) and the mass-adjoint sum (1). The items run in bands of
+// block rows (SymLayout); after each band a fold kernel adds its partials
+// in slot order to FP64 running sums and applies the adjoint epilogue of the
+// reverse walk to the particles it completes.
 #include "common.h"
 
 namespace nb {
@@ -26,17 +27,24 @@ namespace {
 constexpr int TJ = 128;  // sources per LDS tile
 constexpr int NQ = 7;
 
+// One band of the pair pass, as the symmetric force pass (SymLayout): the
+// items of rows I0 <= I < I1; NQF partial rows per particle and slot.
 struct ASymArgs {
     const double *x, *y, *z;
     const float* m;
     const double *lx, *ly, *lz;  // lam_v
     int n, nb;
+    SymBandView band;
     float eps2;
-    float* part;  // [nb][NQ][n]
+    float* part;  // the band's partials (SymBandView::offset)
 };
 
+// The fold of one band, as the symmetric force pass.
 struct ASymFinishArgs {
     const float* part;
+    SymBandView band;
+    double* run;  // [NQF][n] running sums between bands, or nullptr
+    int first;
     int n, nb;
     double G, c, h;
     int update_state;
@@ -157,11 +165,8 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
     __shared__ float4 rl[TJ / 64][128];
     __shared__ float jacc[W][NQ][TJ];
 
-    const int64_t item = blockIdx.x;
-    int J = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) * 0.5);
-    while ((int64_t)J * (J + 1) / 2 > item) --J;
-    while ((int64_t)(J + 1) * (J + 2) / 2 <= item) ++J;
-    const int I = (int)(item - (int64_t)J * (J + 1) / 2);
+    int I, J;
+    band_item(blockIdx.x, a.band.I0, a.band.I1, I, J);
     const bool jside = I != J;
 
     const int tid = threadIdx.x;
@@ -233,17 +238,18 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
 #pragma unroll
                 for (int v = 0; v < W; ++v) sum += jacc[v][Q0 + r][jj];
                 const int j = jt + jj;
-                if (j < je) a.part[((size_t)I * NQF + r) * a.n + j] = -sum;
+                // slot I of particle j
+                if (j < je) a.part[a.band.offset(I, r, j)] = -sum;
             }
         }
     }
+    // slot J of the sinks of block I
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
         if (i >= a.n) continue;
 #pragma unroll
-        for (int p = Q0; p < NQ; ++p)
-            a.part[((size_t)J * NQF + (p - Q0)) * a.n + i] = float(s[k][p].total());
+        for (int p = Q0; p < NQ; ++p) a.part[a.band.offset(J, p - Q0, i)] = float(s[k][p].total());
     }
 }
 
@@ -253,15 +259,31 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
 template <bool F>
 __global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs a) {
     constexpr int Q0 = QRange<F>::lo, NQF = QRange<F>::n;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const SymBandView& b = a.band;
+    const int i = b.base + blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     double q[NQ] = {0, 0, 0, 0, 0, 0, 0};
-    // eight slots' loads in flight together, the adds in slot order
-#pragma unroll 8
-    for (int k = 0; k < a.nb; ++k) {
-        const float* p = a.part + (size_t)k * NQF * a.n + i;
+    if (!a.first) {
 #pragma unroll
-        for (int c = Q0; c < NQ; ++c) q[c] += double(p[(size_t)(c - Q0) * a.n]);
+        for (int c = Q0; c < NQ; ++c) q[c] = a.run[(size_t)(c - Q0) * a.n + i];
+    }
+    // slots I0 .. I1-1 (region A): eight slots' loads in flight together,
+    // the adds in slot order
+#pragma unroll 8
+    for (int k = b.I0; k < b.I1; ++k) {
+#pragma unroll
+        for (int c = Q0; c < NQ; ++c) q[c] += double(a.part[b.offset(k, c - Q0, i)]);
+    }
+    if (i >= b.base + b.nbp) {  // a later band adds this particle's next slots
+#pragma unroll
+        for (int c = Q0; c < NQ; ++c) a.run[(size_t)(c - Q0) * a.n + i] = q[c];
+        return;
+    }
+    // the band's own particles: slots I1 .. nb-1 (region B), then finish
+#pragma unroll 8
+    for (int k = b.I1; k < a.nb; ++k) {
+#pragma unroll
+        for (int c = Q0; c < NQ; ++c) q[c] += double(a.part[b.offset(k, c - Q0, i)]);
     }
     const double G = a.G, c = a.c;
     a.gx[i] = a.gx[i] + c * (G * q[3]);
@@ -295,7 +317,8 @@ __global__ __launch_bounds__(256) void adjoint_sym_finish_kernel(ASymFinishArgs 
 
 template <int W, int K>
 hipError_t launch_asym(const ASymArgs& a, bool force, hipStream_t stream) {
-    const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
+    const int64_t R = a.band.I1 - a.band.I0;
+    const int64_t items = R * (R + 1) / 2 + R * (a.nb - a.band.I1);  // < 2^31 / threads (sym_band_end)
     if (force)
         hipLaunchKernelGGL((adjoint_sym_kernel<W, K, true>), dim3((unsigned)items), dim3(W * 64), 0,
                            stream, a);
@@ -305,23 +328,29 @@ hipError_t launch_asym(const ASymArgs& a, bool force, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Blocks grow while the partials pass 32 GiB, and the largest block is used
-// while its partials fit 64 GiB. (At 2^20 blocks of 1024 -- 30 GB of
-// partials -- run 4 % faster with the force sums and 10 % without them than
-// blocks of 2048 with 15 GB; blocks of 512, 60 GB, gain nothing more.)
-constexpr size_t kAdjSymWorkspaceCap = size_t(32) << 30;
-constexpr size_t kAdjSymWorkspaceMax = size_t(64) << 30;
+// Blocks grow while every partial of the pass at once would pass 32 GiB
+// (at 2^20 blocks of 1024 -- 30 GB of partials -- run 4 % faster with the
+// force sums and 10 % without them than blocks of 2048 with 15 GB; blocks of
+// 512, 60 GB, gain nothing more).
+constexpr size_t kAdjSymGrowBytes = size_t(32) << 30;
 
 }  // namespace
+
+SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums) {
+    const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
+    return SymLayout{n, bi, (int)((n + bi - 1) / bi), force_sums ? QRange<true>::n : QRange<false>::n,
+                     sizeof(float), sizeof(double)};
+}
 
 SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // Measured on MI355X: two sinks per lane (the seven running sums per
     // sink already take ~126 VGPRs; four take ~254 and halve the waves per
     // SIMD) and blocks of 512 at N = 2^18; blocks are kept to at most n/64
-    // and grown, with more waves per workgroup, while the FP32 partials
-    // (nb * 7 * n floats) would pass 32 GiB (blocks of 1024 at 2^20); the
-    // largest block serves up to 64 GiB of partials (about 2.2 M particles),
-    // the one-sided kernel the sizes beyond.
+    // and grown, with more waves per workgroup (up to 2048 particles), while
+    // every FP32 partial of the pass at once (nb * 7 * n floats) would pass
+    // 32 GiB (blocks of 1024 at 2^20). The pass runs in bands when the
+    // workspace is smaller than that (SymLayout), so it serves every n up to
+    // 2^28.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 31 % faster at 8192;
     // symmetric 12 % faster at 12288, 21 % at 24576).
@@ -331,26 +360,26 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 512 && bi(cands[k + 1]) <= n / 64) ++k;
-    while (k < NC && adjoint_sym_partials_bytes(cands[k], n) > kAdjSymWorkspaceCap) ++k;
-    if (k == NC && adjoint_sym_partials_bytes(cands[NC - 1], n) <= kAdjSymWorkspaceMax) k = NC - 1;
-    return k < NC ? cands[k] : SymShape{0, 0};
-}
-
-size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n) {
-    if (s.waves == 0) return 0;
-    const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
-    const int64_t nb = (n + bi - 1) / bi;
-    return (size_t)nb * NQ * (size_t)n * sizeof(float);
+    while (k + 1 < NC && sym_full_bytes(adjoint_sym_layout(cands[k], n, true)) > kAdjSymGrowBytes) ++k;
+    return cands[k];
 }
 
 hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                               const void* lam_v, double eps, double G, double c,
                               bool update_state, double h, void* acc, void* v, void* lam_x,
-                              double* lam_m, void* ws, hipStream_t stream, void* drift_x,
-                              double drift_dt, bool* drifted) {
+                              double* lam_m, void* ws, size_t ws_bytes, hipStream_t stream,
+                              void* drift_x, double drift_dt, bool* drifted) {
     if (drifted) *drifted = false;
-    const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
-    if (bi == 0) return hipErrorInvalidValue;
+    if ((int64_t)sh.waves * sh.ipl == 0) return hipErrorInvalidValue;
+    // the layout of this pass: seven partial rows with the force sums, four
+    // without (the workspace is sized for seven)
+    const SymLayout L = adjoint_sym_layout(sh, n, update_state);
+    const SymPlan plan = sym_plan(L, ws_bytes, sh.waves * 64);
+    if (!plan.valid) return hipErrorInvalidValue;
+    double* run = plan.one ? nullptr : static_cast<double*>(ws);
+    float* parts = reinterpret_cast<float*>(static_cast<char*>(ws) + plan.parts);
+    const size_t budget = plan.budget;
+
     ASymArgs a{};
     const double* px = static_cast<const double*>(x);
     const double* pl = static_cast<const double*>(lam_v);
@@ -362,19 +391,11 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     a.ly = pl + n;
     a.lz = pl + 2 * n;
     a.n = (int)n;
-    a.nb = (int)((n + bi - 1) / bi);
+    a.nb = L.nb;
     a.eps2 = float(eps) * float(eps);
-    a.part = static_cast<float*>(ws);
-    hipError_t e = hipErrorInvalidValue;
-#define NB_ASYM_CASE(WV, KV) \
-    if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, update_state, stream);
-    NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(16, 2)
-#undef NB_ASYM_CASE
-    if (e != hipSuccess) return e;
     ASymFinishArgs f{};
-    f.part = a.part;
+    f.run = run;
     f.n = a.n;
-    f.nb = a.nb;
     f.G = G;
     f.c = c;
     f.h = h;
@@ -386,21 +407,36 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
     f.vx = pv; f.vy = pv + n; f.vz = pv + 2 * n;
     f.gx = pg; f.gy = pg + n; f.gz = pg + 2 * n;
     f.gm = lam_m;
-    if (drift_x) {  // the finishing kernel runs after every read of x and lam_v
+    if (drift_x) {  // each fold finishes particles after every read of their x and lam_v
         double* prx = static_cast<double*>(drift_x);
         double* prl = static_cast<double*>(const_cast<void*>(lam_v));
         f.rx = prx; f.ry = prx + n; f.rz = prx + 2 * n;
         f.rlx = prl; f.rly = prl + n; f.rlz = prl + 2 * n;
         f.dt = drift_dt;
     }
+    a.part = parts;
+    f.part = parts;
+    f.nb = L.nb;
+    for (int I0 = 0; I0 < L.nb;) {
+        const int I1 = sym_band_end(L, I0, budget, sh.waves * 64);
+        a.band = f.band = sym_band_view(L, I0, I1);
+        hipError_t e = hipErrorInvalidValue;
+#define NB_ASYM_CASE(WV, KV) \
+    if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, update_state, stream);
+        NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(16, 2)
+#undef NB_ASYM_CASE
+        if (e != hipSuccess) return e;
+        f.first = I0 == 0;
+        const dim3 fg((unsigned)((a.band.np + 255) / 256));
+        if (update_state)
+            hipLaunchKernelGGL(adjoint_sym_finish_kernel<true>, fg, dim3(256), 0, stream, f);
+        else
+            hipLaunchKernelGGL(adjoint_sym_finish_kernel<false>, fg, dim3(256), 0, stream, f);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        I0 = I1;
+    }
     if (drifted) *drifted = drift_x != nullptr;
-    if (update_state)
-        hipLaunchKernelGGL(adjoint_sym_finish_kernel<true>, dim3((unsigned)((n + 255) / 256)),
-                           dim3(256), 0, stream, f);
-    else
-        hipLaunchKernelGGL(adjoint_sym_finish_kernel<false>, dim3((unsigned)((n + 255) / 256)),
-                           dim3(256), 0, stream, f);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace nb

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "nbody.h"
@@ -252,17 +253,165 @@ struct SymShape {
     int waves;  // wavefronts per workgroup
     int ipl;    // sinks per lane
 };
+
+// ---------------------------------------------------------------------------
+// Bands of the symmetric passes (host side).
+//
+// A symmetric pass over nb blocks has one work item per block pair (I, J),
+// I <= J, and every particle of block P receives one partial in each slot
+// k = 0 .. nb-1 (the source side of item (k, P) for k < P, item (P, P), the
+// sink side of item (P, k) for k > P), which a finishing kernel adds in slot
+// order. The items are launched in bands of consecutive rows I0 <= I < I1.
+// A band writes, for every particle from block I0 on, its slots I0 .. I1-1
+// (region A) and, for the particles of its own blocks, their slots I1 ..
+// nb-1 (region B: the sink sides of items (I, J), J >= I1); a fold kernel
+// then adds them, in slot order, to a running sum per particle kept between
+// bands in the finishing type, and finishes the band's own particles, whose
+// slots are then complete and which no later band reads (later bands touch
+// blocks >= I1 only). The sums are therefore bitwise those of one launch
+// over every item, while the scratch is one band's partials plus the
+// running sums. With a workspace that holds every partial the pass is one
+// band (no running sums).
+// ---------------------------------------------------------------------------
+struct SymLayout {
+    int64_t n;    // particles
+    int64_t bi;   // particles per block
+    int nb;       // blocks
+    int nq;       // partial quantities per particle
+    size_t elem;  // bytes of a partial
+    size_t fin;   // bytes of a running-sum element
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of the partials of band [I0, I1): region A then region B.
+inline size_t sym_band_bytes(const SymLayout& L, int I0, int I1) {
+    const int64_t base = (int64_t)I0 * L.bi;
+    const int64_t np = L.n - base;
+    const int64_t nbp = std::min<int64_t>(L.n, (int64_t)I1 * L.bi) - base;
+    return ((size_t)(I1 - I0) * (size_t)np + (size_t)(L.nb - I1) * (size_t)nbp) *
+           (size_t)L.nq * L.elem;
+}
+// Every partial at once (one band).
+inline size_t sym_full_bytes(const SymLayout& L) { return sym_band_bytes(L, 0, L.nb); }
+// The running sums, placed at the start of a banded workspace.
+inline size_t sym_run_bytes(const SymLayout& L) {
+    return align256((size_t)L.nq * (size_t)L.n * L.fin);
+}
+// The least workspace the pass runs in: every partial at once, or one row
+// per band (the first row needs the most) and the running sums, whichever is
+// less (where a single band would launch too many threads, the second: it is
+// then far below the first).
+inline size_t sym_min_bytes(const SymLayout& L) {
+    return std::min(sym_full_bytes(L), sym_run_bytes(L) + sym_band_bytes(L, 0, 1));
+}
+// Workspace the library asks for: every partial up to kSymBandBudget, else
+// bands of about that much.
+constexpr size_t kSymBandBudget = size_t(4) << 30;
+inline size_t sym_default_bytes(const SymLayout& L) {
+    const size_t full = sym_full_bytes(L);
+    if (full <= kSymBandBudget) return full;
+    return sym_run_bytes(L) + std::max(kSymBandBudget, sym_band_bytes(L, 0, 1));
+}
+// How a pass uses a workspace of ws bytes: one band over every item when
+// the workspace holds every partial and the items launch in one grid (fewer
+// than 2^31 threads of nt per item); else the running sums at the start of
+// the workspace and bands of at most `budget` bytes of partials after them.
+// valid = false: the workspace is below sym_min_bytes.
+struct SymPlan {
+    bool valid, one;
+    size_t parts;   // offset of the partials in the workspace
+    size_t budget;  // bytes of partials per band
+};
+inline int64_t sym_band_items(const SymLayout& L, int I0, int I1);
+inline SymPlan sym_plan(const SymLayout& L, size_t ws, int nt) {
+    const size_t full = sym_full_bytes(L);
+    if (ws >= full && sym_band_items(L, 0, L.nb) < (int64_t(1) << 31) / nt)
+        return SymPlan{true, true, 0, full};
+    const size_t run = sym_run_bytes(L);
+    const bool valid = ws >= run + sym_band_bytes(L, 0, 1);
+    return SymPlan{valid, false, run, valid ? ws - run : 0};
+}
+
+// Work items (block pairs) of band [I0, I1).
+inline int64_t sym_band_items(const SymLayout& L, int I0, int I1) {
+    const int64_t R = I1 - I0;
+    return R * (R + 1) / 2 + R * (L.nb - I1);
+}
+// Last row (exclusive) of the band that starts at I0, fits `budget` bytes of
+// partials and launches fewer than 2^31 threads (nt per item): the band
+// grows while both hold (both grow with I1), and is at least one row (at
+// most nb items of <= 1024 threads).
+inline int sym_band_end(const SymLayout& L, int I0, size_t budget, int nt) {
+    const int64_t max_items = (int64_t(1) << 31) / nt - 1;
+    int lo = I0 + 1, hi = L.nb;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (sym_band_bytes(L, I0, mid) <= budget && sym_band_items(L, I0, mid) <= max_items)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Work item t of the band [I0, I1) -> block pair (I, J), I <= J: first the
+// triangle of pairs inside the band (J < I1), then the rectangle of rows
+// I0 .. I1-1 against the blocks J >= I1; in both, items ordered by J, then
+// I, so that consecutive workgroups share their source block.
+__host__ __device__ inline void band_item(int64_t t, int I0, int I1, int& I, int& J) {
+    const int R = I1 - I0;
+    const int64_t tri = (int64_t)R * (R + 1) / 2;
+    if (t < tri) {
+        int j = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((int64_t)j * (j + 1) / 2 > t) --j;
+        while ((int64_t)(j + 1) * (j + 2) / 2 <= t) ++j;
+        I = I0 + (int)(t - (int64_t)j * (j + 1) / 2);
+        J = I0 + j;
+    } else {
+        const int64_t u = t - tri;
+        J = I1 + (int)(u / R);
+        I = I0 + (int)(u % R);
+    }
+}
+
+// Where one band's partials live: element offsets from the start of its
+// partials, region A (slots I0 .. I1-1 of every particle from `base` on,
+// rows of np) followed by region B (slots I1 .. nb-1 of the band's own nbp
+// particles, rows of nbp); quantity c of nq.
+struct SymBandView {
+    int I0, I1;  // the band's rows
+    int base;    // first particle of block I0
+    int np;      // particles base .. n-1
+    int nbp;     // particles of blocks I0 .. I1-1
+    int nq;      // partial quantities per particle and slot
+    // slot k (I0 <= k < nb) of particle p (p < base + nbp when k >= I1)
+    __host__ __device__ size_t offset(int k, int c, int p) const {
+        return k < I1 ? ((size_t)(k - I0) * nq + c) * np + (size_t)(p - base)
+                      : (size_t)(I1 - I0) * nq * np + ((size_t)(k - I1) * nq + c) * nbp +
+                            (size_t)(p - base);
+    }
+};
+inline SymBandView sym_band_view(const SymLayout& L, int I0, int I1) {
+    const int base = (int)(I0 * L.bi);
+    return SymBandView{I0, I1, base, (int)(L.n - base),
+                       (int)(std::min<int64_t>(L.n, I1 * L.bi) - base), L.nq};
+}
+
 SymShape choose_sym_shape(int prec, int64_t n, bool pot = false);
-size_t sym_partials_bytes(int prec, const SymShape& s, int64_t n, bool pot = false);
+// The band layout of the symmetric force pass.
+SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot = false);
 // acc = a(x) (and with kick_v, v <- v + kick_h * acc; with pot, the
-// potential with the j = i term removed); ws holds
-// sym_partials_bytes(prec, sh, n, pot != nullptr) bytes.
-// drift_x / drift_dt / drifted: as launch_force (the finishing kernel always
-// runs after the pair kernel, so the drift is always taken when asked for).
+// potential with the j = i term removed); ws holds ws_bytes >=
+// sym_min_bytes(sym_layout(prec, sh, n, pot != nullptr)) bytes, used in
+// bands as above (one band when it holds every partial).
+// drift_x / drift_dt / drifted: as launch_force (each finishing kernel runs
+// after every read of its particles' positions, so the drift is always taken
+// when asked for).
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
                             const void* m, double eps, double G, void* acc, void* ws,
-                            hipStream_t stream, void* kick_v = nullptr, double kick_h = 0.0,
-                            void* pot = nullptr, void* drift_x = nullptr,
+                            size_t ws_bytes, hipStream_t stream, void* kick_v = nullptr,
+                            double kick_h = 0.0, void* pot = nullptr, void* drift_x = nullptr,
                             double drift_dt = 0.0, bool* drifted = nullptr);
 
 // Fused adjoint pair pass at x with adjoint lam_v: computes a(x), J^T lam_v,
@@ -281,13 +430,16 @@ hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x
                           bool* drifted = nullptr);
 
 // Symmetric form of the fused adjoint pass (NB_MIX_TILEC only), same
-// contract as launch_adjoint; ws holds adjoint_sym_partials_bytes(sh, n).
+// contract as launch_adjoint; ws holds ws_bytes >= sym_min_bytes(
+// adjoint_sym_layout(sh, n, true)) bytes, used in bands as the force pass.
+// force_sums: the layout of a pass that also sums a(x) (seven quantities;
+// four without), which update_state asks for.
 SymShape choose_adjoint_sym_shape(int prec, int64_t n);
-size_t adjoint_sym_partials_bytes(const SymShape& s, int64_t n);
+SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums);
 hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                               const void* lam_v, double eps, double G, double c,
                               bool update_state, double h, void* acc, void* v, void* lam_x,
-                              double* lam_m, void* ws, hipStream_t stream,
+                              double* lam_m, void* ws, size_t ws_bytes, hipStream_t stream,
                               void* drift_x = nullptr, double drift_dt = 0.0,
                               bool* drifted = nullptr);
 
@@ -314,17 +466,18 @@ struct AccelPlan {
     SymShape sym;   // the symmetric pass (sym.waves != 0), or
     Shape sh;       // the one-sided kernel in this shape
     bool self_set;
-    size_t need;    // scratch bytes the pass needs
+    size_t need;    // scratch bytes the pass needs at least
+    size_t full;    // scratch bytes it uses at most (every partial at once)
 };
 // Checks the arguments of nbody_accel / nbody_accel_ex (not the workspace)
 // and fills *plan; returns an nb_status.
 int accel_plan(int64_t ni, const void* xi, int64_t nj, const void* xj, const void* mj,
                double eps, double G, int prec, void* acc, void* pot, const nb_launch* launch,
                AccelPlan* plan);
-// Enqueues the planned pass with plan.need bytes of scratch at ws.
+// Enqueues the planned pass with ws_bytes >= plan.need bytes of scratch at ws.
 hipError_t accel_launch(const AccelPlan& p, int64_t ni, const void* xi, int64_t nj, const void* xj,
                         const void* mj, double eps, double G, int prec, void* acc, void* pot,
-                        void* ws, hipStream_t s);
+                        void* ws, size_t ws_bytes, hipStream_t s);
 // NB_OK if a gfx950 device is current, else NB_ENODEV.
 int check_device();
 // NB_OK, or NB_EDEVICE after recording the HIP error for nbody_last_hip_error.

@@ -28,7 +28,10 @@
 //    exactly one partial in each slot k = 0 .. nb-1 (k < P: j side of item
 //    (k, P); k = P: item (P, P); k > P: i side of item (P, k)), and a second
 //    kernel adds the nb slots in slot order in FP64, then applies G and the
-//    optional closing half-kick;
+//    optional closing half-kick. The items run in bands of rows I, each band
+//    followed by a kernel that folds the slots it wrote into running sums
+//    (SymLayout): the sums are bitwise those of one launch, and the scratch
+//    is one band's partials;
 //  * with the potential, the same reciprocal square root also gives the
 //    fourth quantity: m_j / r on the i side and m_i / r on the j side (no
 //    sign change, the potential is symmetric). The diagonal items include
@@ -69,18 +72,27 @@ using SymTileC = SymPol<double, float, float, SumTile, double>;
 using SymF32 = SymPol<float, float, float, SumPlain<float>, float>;
 using SymF64 = SymPol<double, double, double, SumPlain<double>, double>;
 
+// One band of the pair pass: the items of rows I0 <= I < I1 (see SymLayout).
+// NQ = 3 partial quantities, or 4 with the potential.
 template <class Pol>
 struct SymArgs {
     const typename Pol::pos_t *x, *y, *z;
     const typename Pol::mass_t* m;
     int n, nb;
+    SymBandView band;
     typename Pol::calc_t eps2;
-    typename Pol::calc_t* part;  // [nb][NQ][n], NQ = 3, or 4 with the potential
+    typename Pol::calc_t* part;  // the band's partials (SymBandView::offset)
 };
 
+// The fold of one band: particles base .. n-1 add their slots I0 .. I1-1;
+// the band's own particles also their slots I1 .. nb-1, and are finished;
+// the others keep their running sums for the next band.
 template <class Pol>
 struct SymFinishArgs {
-    const typename Pol::calc_t* part;
+    const typename Pol::calc_t* part;  // the band's partials
+    SymBandView band;
+    typename Pol::fin_t* run;       // [NQ][n] running sums between bands, or nullptr
+    int first;                      // the first band: the sums start at 0
     const typename Pol::mass_t* m;  // for the j = i potential term
     int n, nb;
     typename Pol::calc_t eps2;
@@ -183,12 +195,8 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
     __shared__ V4 rec[TJ / 64][128];
     __shared__ C jacc[W][NQ][TJ];
 
-    // item -> (I, J), I <= J, items ordered by J then I
-    const int64_t item = blockIdx.x;
-    int J = (int)((sqrt(8.0 * (double)item + 1.0) - 1.0) * 0.5);
-    while ((int64_t)J * (J + 1) / 2 > item) --J;
-    while ((int64_t)(J + 1) * (J + 2) / 2 <= item) ++J;
-    const int I = (int)(item - (int64_t)J * (J + 1) / 2);
+    int I, J;
+    band_item(blockIdx.x, a.band.I0, a.band.I1, I, J);
     const bool jside = I != J;
 
     const int tid = threadIdx.x;
@@ -259,41 +267,67 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
 #pragma unroll
                 for (int v = 0; v < W; ++v) sum += jacc[v][c][jj];
                 const int j = jt + jj;
-                if (j < je) a.part[((size_t)I * NQ + c) * a.n + j] = c < 3 ? -sum : sum;
+                // slot I of particle j
+                if (j < je) a.part[a.band.offset(I, c, j)] = c < 3 ? -sum : sum;
             }
         }
         // rec is rewritten only after every wave has passed the barrier above
     }
+    // slot J of the sinks of block I
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
         if (i >= a.n) continue;
 #pragma unroll
-        for (int c = 0; c < NQ; ++c) a.part[((size_t)J * NQ + c) * a.n + i] = C(s[k][c].total());
+        for (int c = 0; c < NQ; ++c) a.part[a.band.offset(J, c, i)] = C(s[k][c].total());
     }
 }
 
-// Adds the nb partials of every particle in slot order (in fin_t: FP64 for
-// the tile-compensated and FP64 policies, FP32 for the FP32 one), then stores
+// The fold of one band (SymFinishArgs): adds a particle's partials in slot
+// order (in fin_t: FP64 for the tile-compensated and FP64 policies, FP32 for
+// the FP32 one) to its running sum; when its slots are complete, stores
 // a = G * sum and applies the optional half-kick v <- v + h a, with a as
 // stored; with P, also the potential -G (sum - m_i / eps).
 template <class Pol, bool P>
 __global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs<Pol> a) {
     using pos_t = typename Pol::pos_t;
     using fin_t = typename Pol::fin_t;
+    using calc_t = typename Pol::calc_t;
     constexpr int NQ = P ? 4 : 3;
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const SymBandView& b = a.band;
+    const int i = b.base + blockIdx.x * 256 + threadIdx.x;
     if (i >= a.n) return;
     fin_t sx = 0, sy = 0, sz = 0, sp = 0;
-    // unrolled so that the loads of eight slots are in flight together (the
-    // adds stay in slot order); at small n the pass is latency-bound here
+    if (!a.first) {
+        sx = a.run[i];
+        sy = a.run[(size_t)a.n + i];
+        sz = a.run[(size_t)2 * a.n + i];
+        if (P) sp = a.run[(size_t)3 * a.n + i];
+    }
+    // slots I0 .. I1-1 (region A), unrolled so that the loads of eight slots
+    // are in flight together (the adds stay in slot order; at small n the
+    // pass is latency-bound here)
 #pragma unroll 8
-    for (int k = 0; k < a.nb; ++k) {
-        const typename Pol::calc_t* p = a.part + (size_t)k * NQ * a.n;
-        sx += fin_t(p[i]);
-        sy += fin_t(p[(size_t)a.n + i]);
-        sz += fin_t(p[(size_t)2 * a.n + i]);
-        if (P) sp += fin_t(p[(size_t)3 * a.n + i]);
+    for (int k = b.I0; k < b.I1; ++k) {
+        sx += fin_t(a.part[b.offset(k, 0, i)]);
+        sy += fin_t(a.part[b.offset(k, 1, i)]);
+        sz += fin_t(a.part[b.offset(k, 2, i)]);
+        if (P) sp += fin_t(a.part[b.offset(k, 3, i)]);
+    }
+    if (i >= b.base + b.nbp) {  // a later band adds this particle's next slots
+        a.run[i] = sx;
+        a.run[(size_t)a.n + i] = sy;
+        a.run[(size_t)2 * a.n + i] = sz;
+        if (P) a.run[(size_t)3 * a.n + i] = sp;
+        return;
+    }
+    // the band's own particles: slots I1 .. nb-1 (region B), then finish
+#pragma unroll 8
+    for (int k = b.I1; k < a.nb; ++k) {
+        sx += fin_t(a.part[b.offset(k, 0, i)]);
+        sy += fin_t(a.part[b.offset(k, 1, i)]);
+        sz += fin_t(a.part[b.offset(k, 2, i)]);
+        if (P) sp += fin_t(a.part[b.offset(k, 3, i)]);
     }
     if (P) {
         // the j = i term as the pair loop formed it: m_i times the
@@ -326,7 +360,8 @@ __global__ __launch_bounds__(256) void force_sym_finish_kernel(SymFinishArgs<Pol
 
 template <class Pol, int W, int K>
 hipError_t launch_sym(const SymArgs<Pol>& a, bool pot, hipStream_t stream) {
-    const int64_t items = (int64_t)a.nb * (a.nb + 1) / 2;
+    const int64_t R = a.band.I1 - a.band.I0;
+    const int64_t items = R * (R + 1) / 2 + R * (a.nb - a.band.I1);  // < 2^31 / threads (sym_band_end)
     if (pot)
         hipLaunchKernelGGL((force_sym_kernel<Pol, W, K, true>), dim3((unsigned)items), dim3(W * 64),
                            0, stream, a);
@@ -338,11 +373,21 @@ hipError_t launch_sym(const SymArgs<Pol>& a, bool pot, hipStream_t stream) {
 
 template <class Pol>
 hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, double eps,
-                   double G, void* acc, void* ws, hipStream_t stream, void* kick_v,
-                   double kick_h, void* pot, void* drift_x, double drift_dt) {
+                   double G, void* acc, void* ws, size_t ws_bytes, hipStream_t stream,
+                   void* kick_v, double kick_h, void* pot, void* drift_x, double drift_dt) {
     using pos_t = typename Pol::pos_t;
     using calc_t = typename Pol::calc_t;
+    using fin_t = typename Pol::fin_t;
     const int64_t bi = (int64_t)sh.waves * 64 * sh.ipl;
+    const SymLayout L{n, bi, (int)((n + bi - 1) / bi), pot ? 4 : 3, sizeof(calc_t), sizeof(fin_t)};
+    // one band when the workspace holds every partial; else the running sums
+    // first, then one band's partials at a time
+    const SymPlan plan = sym_plan(L, ws_bytes, sh.waves * 64);
+    if (!plan.valid) return hipErrorInvalidValue;
+    fin_t* run = plan.one ? nullptr : static_cast<fin_t*>(ws);
+    calc_t* parts = reinterpret_cast<calc_t*>(static_cast<char*>(ws) + plan.parts);
+    const size_t budget = plan.budget;
+
     SymArgs<Pol> a{};
     const pos_t* p = static_cast<const pos_t*>(x);
     a.x = p;
@@ -350,20 +395,12 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
     a.z = p + 2 * n;
     a.m = static_cast<const typename Pol::mass_t*>(m);
     a.n = (int)n;
-    a.nb = (int)((n + bi - 1) / bi);
+    a.nb = L.nb;
     a.eps2 = calc_t(eps) * calc_t(eps);
-    a.part = static_cast<calc_t*>(ws);
-    hipError_t e = hipErrorInvalidValue;
-#define NB_SYM_CASE(WV, KV) \
-    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<Pol, WV, KV>(a, pot != nullptr, stream);
-    NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
-#undef NB_SYM_CASE
-    if (e != hipSuccess) return e;
     SymFinishArgs<Pol> f{};
-    f.part = a.part;
+    f.run = run;
     f.m = a.m;
     f.n = a.n;
-    f.nb = a.nb;
     f.eps2 = a.eps2;
     f.G = G;
     f.pot = static_cast<pos_t*>(pot);
@@ -385,32 +422,52 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
             f.dt = drift_dt;
         }
     }
-    const dim3 fg((unsigned)((n + 255) / 256));
-    if (pot)
-        hipLaunchKernelGGL((force_sym_finish_kernel<Pol, true>), fg, dim3(256), 0, stream, f);
-    else
-        hipLaunchKernelGGL((force_sym_finish_kernel<Pol, false>), fg, dim3(256), 0, stream, f);
-    return hipGetLastError();
+    a.part = parts;
+    f.part = parts;
+    f.nb = L.nb;
+    for (int I0 = 0; I0 < L.nb;) {
+        const int I1 = sym_band_end(L, I0, budget, sh.waves * 64);
+        a.band = f.band = sym_band_view(L, I0, I1);
+        hipError_t e = hipErrorInvalidValue;
+#define NB_SYM_CASE(WV, KV) \
+    if (sh.waves == WV && sh.ipl == KV) e = launch_sym<Pol, WV, KV>(a, pot != nullptr, stream);
+        NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+#undef NB_SYM_CASE
+        if (e != hipSuccess) return e;
+        f.first = I0 == 0;
+        const dim3 fg((unsigned)((a.band.np + 255) / 256));
+        if (pot)
+            hipLaunchKernelGGL((force_sym_finish_kernel<Pol, true>), fg, dim3(256), 0, stream, f);
+        else
+            hipLaunchKernelGGL((force_sym_finish_kernel<Pol, false>), fg, dim3(256), 0, stream, f);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        I0 = I1;
+    }
+    return hipSuccess;
 }
 
-// Blocks grow while the partials pass kSymWorkspaceCap; where even the
-// largest block passes it, the largest is still used while its partials fit
-// kSymWorkspaceMax (under a quarter of the 288 GB of HBM), and only beyond
-// that the one-sided kernel takes over.
-constexpr size_t kSymWorkspaceCap = size_t(16) << 30;
-constexpr size_t kSymWorkspaceMax = size_t(64) << 30;
+// Blocks grow while every partial of the pass at once would pass
+// kSymGrowBytes (larger blocks, fewer partials to write and read back).
+constexpr size_t kSymGrowBytes = size_t(16) << 30;
 
 }  // namespace
+
+SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
+    const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
+    const size_t elem = prec == NB_F64 ? sizeof(double) : sizeof(float);  // partial type
+    const size_t fin = prec == NB_F32 ? sizeof(float) : sizeof(double);   // running sum type
+    return SymLayout{n, bi, (int)((n + bi - 1) / bi), pot ? 4 : 3, elem, fin};
+}
 
 SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // Measured on MI355X at N = 2^18 and 2^20: four-wave workgroups with four
     // sinks per lane (blocks of 1024) are fastest -- more waves per SIMD than
     // the larger workgroups, and one source rotation per four pairs. Blocks
     // are kept to at most n/48 (>= 1176 equal work items for the 256 CUs),
-    // and grown only when the FP32 partials (nb * 3 * n floats, or
-    // nb * 4 * n with the potential) would pass 16 GiB; the largest block
-    // serves up to 64 GiB of partials (about 4.8 M particles), the one-sided
-    // kernel the sizes beyond.
+    // and grown (up to 4096) only while every FP32 partial of the pass at
+    // once (nb * 3 * n floats, or nb * 4 * n with the potential) would pass
+    // 16 GiB. The pass runs in bands when the workspace is smaller than that
+    // (SymLayout), so it serves every n up to 2^28.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
@@ -422,35 +479,26 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
     while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48) ++k;
-    while (k < NC && sym_partials_bytes(prec, cands[k], n, pot) > kSymWorkspaceCap) ++k;
-    if (k == NC && sym_partials_bytes(prec, cands[NC - 1], n, pot) <= kSymWorkspaceMax) k = NC - 1;
-    return k < NC ? cands[k] : SymShape{0, 0};
-}
-
-size_t sym_partials_bytes(int prec, const SymShape& s, int64_t n, bool pot) {
-    if (s.waves == 0) return 0;
-    const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
-    const int64_t nb = (n + bi - 1) / bi;
-    const size_t elem = prec == NB_F64 ? sizeof(double) : sizeof(float);  // partial type
-    return (size_t)nb * (pot ? 4 : 3) * (size_t)n * elem;
+    while (k + 1 < NC && sym_full_bytes(sym_layout(prec, cands[k], n, pot)) > kSymGrowBytes) ++k;
+    return cands[k];
 }
 
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,
                             const void* m, double eps, double G, void* acc, void* ws,
-                            hipStream_t stream, void* kick_v, double kick_h, void* pot,
-                            void* drift_x, double drift_dt, bool* drifted) {
+                            size_t ws_bytes, hipStream_t stream, void* kick_v, double kick_h,
+                            void* pot, void* drift_x, double drift_dt, bool* drifted) {
     if ((int64_t)sh.waves * sh.ipl == 0) return hipErrorInvalidValue;
     if (!kick_v) drift_x = nullptr;
     if (drifted) *drifted = drift_x != nullptr;
     if (prec == NB_MIX_TILEC)
-        return run_sym<SymTileC>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot,
-                                 drift_x, drift_dt);
+        return run_sym<SymTileC>(sh, n, x, m, eps, G, acc, ws, ws_bytes, stream, kick_v, kick_h,
+                                 pot, drift_x, drift_dt);
     if (prec == NB_F32)
-        return run_sym<SymF32>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot,
-                               drift_x, drift_dt);
+        return run_sym<SymF32>(sh, n, x, m, eps, G, acc, ws, ws_bytes, stream, kick_v, kick_h,
+                               pot, drift_x, drift_dt);
     if (prec == NB_F64)
-        return run_sym<SymF64>(sh, n, x, m, eps, G, acc, ws, stream, kick_v, kick_h, pot,
-                               drift_x, drift_dt);
+        return run_sym<SymF64>(sh, n, x, m, eps, G, acc, ws, ws_bytes, stream, kick_v, kick_h,
+                               pot, drift_x, drift_dt);
     return hipErrorInvalidValue;
 }
 

@@ -252,8 +252,13 @@ int accel_plan(int64_t ni, const void* xi, int64_t nj, const void* xj, const voi
     }
     plan->sh = sh;
     plan->self_set = self_set;
-    plan->need = plan->sym.waves ? sym_partials_bytes(prec, plan->sym, ni, pot != nullptr)
-                                 : accel_ws(sh, ni);
+    if (plan->sym.waves) {
+        const SymLayout L = sym_layout(prec, plan->sym, ni, pot != nullptr);
+        plan->need = sym_min_bytes(L);
+        plan->full = sym_full_bytes(L);
+    } else {
+        plan->need = plan->full = accel_ws(sh, ni);
+    }
     return NB_OK;
 }
 
@@ -277,10 +282,11 @@ namespace nb {
 
 hipError_t accel_launch(const AccelPlan& p, int64_t ni, const void* xi, int64_t nj, const void* xj,
                         const void* mj, double eps, double G, int prec, void* acc, void* pot,
-                        void* ws, hipStream_t s) {
+                        void* ws, size_t ws_bytes, hipStream_t s) {
     return timed(NB_PROF_FORCE, s, [&] {
         if (p.sym.waves)
-            return launch_force_sym(prec, p.sym, ni, xi, mj, eps, G, acc, ws, s, nullptr, 0.0, pot);
+            return launch_force_sym(prec, p.sym, ni, xi, mj, eps, G, acc, ws, ws_bytes, s,
+                                    nullptr, 0.0, pot);
         return launch_force(prec, p.sh, ni, xi, nj, xj, mj, eps, G, p.self_set, acc, pot, ws, s);
     });
 }
@@ -296,9 +302,12 @@ int accel_common(int64_t ni, const void* xi, int64_t nj, const void* xj, const v
     int st = accel_plan(ni, xi, nj, xj, mj, eps, G, prec, acc, pot, launch, &plan);
     if (st != NB_OK) return st;
     if ((st = check_ws(ws, ws_bytes, plan.need)) != NB_OK) return st;
-    if (accel_ws_overlaps(ws, plan.need, ni, xi, nj, xj, mj, prec, acc, pot)) return NB_EINVAL;
+    // the bytes the pass may use: a banded pass uses what it is given, up to
+    // every partial at once
+    const size_t used = std::min(ws_bytes, plan.full);
+    if (accel_ws_overlaps(ws, used, ni, xi, nj, xj, mj, prec, acc, pot)) return NB_EINVAL;
     if ((st = check_device()) != NB_OK) return st;
-    return hip_status(accel_launch(plan, ni, xi, nj, xj, mj, eps, G, prec, acc, pot, ws,
+    return hip_status(accel_launch(plan, ni, xi, nj, xj, mj, eps, G, prec, acc, pot, ws, used,
                                    static_cast<hipStream_t>(stream)));
 }
 
@@ -340,12 +349,14 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
     }
     const Shape sh = choose_force_shape(prec, n, n);
     const SymShape sym = choose_sym_shape(prec, n);
-    const size_t need = sym.waves ? sym_partials_bytes(prec, sym, n) : accel_ws(sh, n);
+    const SymLayout L = sym.waves ? sym_layout(prec, sym, n) : SymLayout{};
+    const size_t need = sym.waves ? sym_min_bytes(L) : accel_ws(sh, n);
     int st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
-    if (need && (overlaps(ws, need, x, vb) || overlaps(ws, need, v, vb) ||
-                 overlaps(ws, need, m, (size_t)n * ms) || overlaps(ws, need, acc, vb) ||
-                 (ckpt && overlaps(ws, need, ckpt, (size_t)(nsteps / ckpt_every + 1) * 3 * vb))))
+    const size_t used = sym.waves ? std::min(ws_bytes, sym_full_bytes(L)) : need;
+    if (used && (overlaps(ws, used, x, vb) || overlaps(ws, used, v, vb) ||
+                 overlaps(ws, used, m, (size_t)n * ms) || overlaps(ws, used, acc, vb) ||
+                 (ckpt && overlaps(ws, used, ckpt, (size_t)(nsteps / ckpt_every + 1) * 3 * vb))))
         return NB_EINVAL;
     if ((st = check_device()) != NB_OK) return st;
 
@@ -362,7 +373,7 @@ int nbody_step(int64_t n, void* x, void* v, const void* m, void* acc, double eps
                 void* kv = kick ? v : nullptr;
                 void* dx = (kick && drift) ? x : nullptr;
                 if (sym.waves)
-                    return launch_force_sym(prec, sym, n, x, m, eps, G, acc, ws, q, kv, h, nullptr,
+                    return launch_force_sym(prec, sym, n, x, m, eps, G, acc, ws, used, q, kv, h, nullptr,
                                             dx, dt, drifted);
                 return launch_force(prec, sh, n, x, n, x, m, eps, G, true, acc, nullptr, ws, q, kv,
                                     h, dx, dt, drifted);
@@ -468,15 +479,17 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
     }
     const Shape sh = choose_adjoint_shape(prec, n);
     const SymShape sym = choose_adjoint_sym_shape(prec, n);
-    const size_t need = sym.waves ? adjoint_sym_partials_bytes(sym, n)
+    const size_t need = sym.waves ? sym_min_bytes(adjoint_sym_layout(sym, n, true))
                                   : (sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0);
     int st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
-    if (need) {
-        if (overlaps(ws, need, m, (size_t)n * ms)) return NB_EINVAL;
+    const size_t used = sym.waves ? std::min(ws_bytes, sym_full_bytes(adjoint_sym_layout(sym, n, true)))
+                                  : need;
+    if (used) {
+        if (overlaps(ws, used, m, (size_t)n * ms)) return NB_EINVAL;
         for (int p = 0; p < 6; ++p)
-            if (overlaps(ws, need, bufs[p], sizes[p])) return NB_EINVAL;
-        if (ckpt && overlaps(ws, need, ckpt, (size_t)(step_end / ckpt_every + 1) * 3 * vb))
+            if (overlaps(ws, used, bufs[p], sizes[p])) return NB_EINVAL;
+        if (ckpt && overlaps(ws, used, ckpt, (size_t)(step_end / ckpt_every + 1) * 3 * vb))
             return NB_EINVAL;
     }
     if ((st = check_device()) != NB_OK) return st;
@@ -495,7 +508,7 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
             void* dx = drift ? x : nullptr;
             if (sym.waves)
                 return launch_adjoint_sym(sym, n, x, m, lam_v, eps, G, c, update_state, h, acc, v,
-                                          lam_x, lm, ws, s, dx, dt, &drifted);
+                                          lam_x, lm, ws, used, s, dx, dt, &drifted);
             return launch_adjoint(prec, sh, n, x, m, lam_v, eps, G, c, update_state, h, acc, v, lam_x,
                                   lm, ws, s, dx, dt, &drifted);
         });
@@ -569,22 +582,41 @@ int diffusion3d_step(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, d
     }));
 }
 
+size_t nbody_accel_workspace_size(int64_t ni, int64_t nj, int prec, int self_set, int potential,
+                                  const nb_launch* launch) {
+    if (!valid_prec(prec) || ni < 1 || nj < 1 || ni > kMaxN || nj > kMaxN) return 0;
+    if (self_set && ni != nj) return 0;
+    const SymShape sym = (self_set && !launch) ? choose_sym_shape(prec, ni, potential != 0)
+                                               : SymShape{0, 0};
+    if (sym.waves) return sym_default_bytes(sym_layout(prec, sym, ni, potential != 0));
+    Shape sh = choose_force_shape(prec, ni, nj);
+    if (launch) {
+        if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
+        if (launch->block) sh.block = launch->block;
+        if (launch->split) sh.split = launch->split;
+        if (!shape_supported(sh)) return 0;
+    }
+    return accel_ws(sh, ni);
+}
+
 size_t nbody_workspace_size(int op, int64_t n, int prec) {
     if (!valid_prec(prec) || n < 1 || n > kMaxN) return 0;
     switch (op) {
     case NB_OP_ACCEL: {  // any ni, nj <= n; either pass, with or without the potential
         const size_t a = std::max(accel_ws(choose_force_shape(prec, n, n), n), force_partials_bound(n));
-        const size_t b = sym_partials_bytes(prec, choose_sym_shape(prec, n), n);
-        const size_t c = sym_partials_bytes(prec, choose_sym_shape(prec, n, true), n, true);
+        const SymShape s0 = choose_sym_shape(prec, n), s1 = choose_sym_shape(prec, n, true);
+        const size_t b = s0.waves ? sym_default_bytes(sym_layout(prec, s0, n)) : 0;
+        const size_t c = s1.waves ? sym_default_bytes(sym_layout(prec, s1, n, true)) : 0;
         return std::max(a, std::max(b, c));
     }
     case NB_OP_STEP: {
         const SymShape sym = choose_sym_shape(prec, n);
-        return sym.waves ? sym_partials_bytes(prec, sym, n) : accel_ws(choose_force_shape(prec, n, n), n);
+        return sym.waves ? sym_default_bytes(sym_layout(prec, sym, n))
+                         : accel_ws(choose_force_shape(prec, n, n), n);
     }
     case NB_OP_ADJOINT: {
         const SymShape sym = choose_adjoint_sym_shape(prec, n);
-        if (sym.waves) return adjoint_sym_partials_bytes(sym, n);
+        if (sym.waves) return sym_default_bytes(adjoint_sym_layout(sym, n, true));
         const Shape sh = choose_adjoint_shape(prec, n);
         return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
     }

@@ -57,5 +57,6 @@ extern "C" int nbody_accel_noalloc(int64_t ni, const void* xi, int64_t nj, const
     void* ws = nullptr;
     if (plan.need > 0 && (st = scratch_address(&ws)) != NB_OK) return st;
     return hip_status(accel_launch(plan, ni, xi, nj, xj, mj, eps, G, prec, acc, pot, ws,
+                                   std::min(kScratchBytes, plan.full),
                                    static_cast<hipStream_t>(stream)));
 }

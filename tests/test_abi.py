@@ -67,39 +67,52 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
     # a set acting on itself with the tile-compensated policy from 12288 on:
     # the symmetric pass, one FP32 partial per particle, component and block
-    # (blocks of at most min(n/48, 1024) particles, larger while the partials
-    # would pass 16 GiB)
+    # (blocks of at most min(n/48, 1024) particles, larger while every partial
+    # at once would pass 16 GiB); the whole set of partials up to 4 GiB
     assert L.nbody_workspace_size(1, 12288, TILEC) == 48 * 3 * 12288 * 4
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
     assert L.nbody_workspace_size(1, 24576, TILEC) == 48 * 3 * 24576 * 4
     assert L.nbody_workspace_size(1, 32768, TILEC) == 64 * 3 * 32768 * 4
-    assert L.nbody_workspace_size(1, 1 << 20, TILEC) == 1024 * 3 * (1 << 20) * 4
-    assert L.nbody_workspace_size(1, 1 << 21, TILEC) == 512 * 3 * (1 << 21) * 4
-    # past 16 GiB with the largest block (4096), the largest block up to 64 GiB
-    assert L.nbody_workspace_size(1, 3 << 20, TILEC) == 768 * 3 * (3 << 20) * 4
-    assert L.nbody_workspace_size(1, 5 << 20, TILEC) < 1 << 30  # one-sided kernel
-    assert L.nbody_workspace_size(0, 1 << 20, TILEC) >= L.nbody_workspace_size(1, 1 << 20, TILEC)
+    assert L.nbody_workspace_size(1, 1 << 18, TILEC) == 256 * 3 * (1 << 18) * 4
+    # beyond 4 GiB of partials the pass runs in bands of about 4 GiB, after
+    # FP64 running sums (3 per particle)
+    G4 = 4 << 30
+    for n in (1 << 20, 1 << 21, 3 << 20, 5 << 20):
+        assert L.nbody_workspace_size(1, n, TILEC) == 3 * n * 8 + G4, n
+    # ... or one row of blocks per band where a row needs more (2^28: blocks
+    # of 4096, a row holds the slot of every particle and the 65535 other
+    # slots of its own 4096)
+    n = 1 << 28
+    assert L.nbody_workspace_size(1, n, TILEC) == 3 * n * 8 + 3 * 4 * (n + 65535 * 4096)
+    # FP32: FP32 running sums; FP64: FP64 partials
+    assert L.nbody_workspace_size(1, 1 << 20, F32) == 3 * (1 << 20) * 4 + G4
+    assert L.nbody_workspace_size(1, 1 << 20, F64) == 3 * (1 << 20) * 8 + G4
+    assert L.nbody_workspace_size(1, 1 << 17, F64) == 128 * 3 * (1 << 17) * 8
     # nbody_accel covers the symmetric pass with the potential too: four
-    # partials per particle and block, the block grown by the same bound
-    assert L.nbody_workspace_size(0, 1 << 20, TILEC) == 1024 * 4 * (1 << 20) * 4
+    # partials (and running sums) per particle
+    assert L.nbody_workspace_size(0, 1 << 20, TILEC) == 4 * (1 << 20) * 8 + G4
+    assert L.nbody_workspace_size(0, 1 << 18, TILEC) == 256 * 4 * (1 << 18) * 4
     # and a small sink set against up to n sources: at most 64 one-tile source
     # ranges below 16384 sources, n / 512 above, <= 2^24 sink-ranges in all,
     # 4 FP64 partials each
     assert L.nbody_workspace_size(0, 16384, TILEC) == 64 * 16384 * 4 * 8
     assert L.nbody_workspace_size(0, 1 << 30, TILEC) == (1 << 24) * 4 * 8
     assert L.nbody_workspace_size(0, 1 << 30, F64) == (1 << 24) * 4 * 8
-    # (at 1,200,000 the potential pass takes blocks of 2048, 586 x 4 partials,
-    # and the pass without it still 1172 x 3)
-    assert L.nbody_workspace_size(0, 1_200_000, TILEC) == 1172 * 3 * 1_200_000 * 4
     # and the symmetric adjoint pass: seven FP32 partials per particle and
-    # block (blocks of min(n/64, 512), larger while past 32 GiB, up to 2048)
+    # block (blocks of min(n/64, 512), larger while every partial would pass
+    # 32 GiB, up to 2048), all of them up to 4 GiB, then seven FP64 running
+    # sums and bands of about 4 GiB
     assert L.nbody_workspace_size(2, 12288, TILEC) == 48 * 7 * 12288 * 4
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
+    assert L.nbody_workspace_size(2, 1 << 17, TILEC) == 256 * 7 * (1 << 17) * 4
     assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
-    assert L.nbody_workspace_size(2, 1 << 20, TILEC) == 1024 * 7 * (1 << 20) * 4
-    assert L.nbody_workspace_size(2, 1 << 21, TILEC) == 1024 * 7 * (1 << 21) * 4
-    assert L.nbody_workspace_size(2, 3 << 20, TILEC) < 1 << 30  # one-sided kernel
+    for n in (1 << 19, 1 << 20, 1 << 21, 3 << 20):
+        assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + G4, n
+    n = 1 << 28
+    assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + 7 * 4 * (n + 131071 * 2048)
+    # the one-sided adjoint kernel (other policies): split partials or none
+    assert L.nbody_workspace_size(2, 1 << 20, F64) == 8 * 7 * (1 << 20) * 8
 
 
 def _skip_if_device(L):
@@ -264,10 +277,18 @@ def test_pass_info(L):
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 512, 2, 1024)
     assert L.nbody_pass_info(1, 1 << 20, 2, ctypes.byref(info)) == 0  # FP32 running sums
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
-    # FP64: FP64 partials, so the blocks grow to 2048 at 2^20 to stay within 16 GiB
+    # FP64: FP64 partials, so the blocks grow to 2048 at 2^20 (every partial
+    # at once would pass 16 GiB with 1024)
     assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
     assert (info.symmetric, info.block_particles) == (1, 2048)
-    assert info.workspace_bytes == 512 * 3 * (1 << 20) * 8
+    assert info.workspace_bytes == 3 * (1 << 20) * 8 + (4 << 30)
+    # the symmetric passes now serve every size up to 2^28: blocks of 4096
+    # (force) and 2048 (adjoint) at the top
+    for op, b in ((1, 4096), (2, 2048)):
+        assert L.nbody_pass_info(op, 1 << 28, TILEC, ctypes.byref(info)) == 0
+        assert (info.symmetric, info.block_particles) == (1, b)
+    assert L.nbody_pass_info(1, (1 << 28) + 1, TILEC, ctypes.byref(info)) == 0
+    assert info.symmetric == 0
     assert L.nbody_pass_info(2, 1 << 20, F64, ctypes.byref(info)) == 0 and info.symmetric == 0
     assert L.nbody_pass_info(1, 1000, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
     # the symmetric passes start at 12288 particles

@@ -77,3 +77,65 @@ def test_fp32_workload_energy_drift():
     print("fp32-65536 energy drift: GPU %.3e, oracle %.3e at step 100; max |difference| %.3e"
           % (d_gpu[-1], d_ref[-1], np.abs(d_gpu - d_ref).max()))
     assert np.abs(d_gpu - d_ref).max() <= 1e-5
+
+
+def _f64_force_parity(xd, md, eps, name, seed):
+    """Sampled sinks of the FP64 force pass against the oracle: <= 1e-12."""
+    import oracle
+    from tests.gpu_util import cluster_centres, sample_indices
+    a = host(nb.accel(xd, md, eps, prec="f64"))
+    xs, ms = host(xd), host(md)
+    idx = sample_indices(xs, 256, 32, seed=seed, centres=cluster_centres(name, xs))
+    e = rel(a[:, idx], oracle.accel_sampled(xs, ms, eps, idx))
+    return e
+
+
+@pytest.mark.parametrize("name", ["subcluster-262144", "scale-2^20"])
+def test_workload_energy_drift_per_variant(name):
+    """The workloads' trajectories as the workload descriptions ask: 20 steps
+    (subcluster, every mixed variant) or 10 steps (2^20, tile-compensated)
+    against an FP64 trajectory run on the GPU, whose force pass first passes
+    the sampled <= 1e-12 parity check against the oracle at the initial and
+    at the final state. Per variant: the energy drift dE = (E_S - E_0)/|E_0|
+    (FP64 diagnostics) differs from the FP64 trajectory's by less than the
+    work a force error of 1e-5 could do over the run, and the final positions
+    differ by less than 1e-5 of the distance travelled."""
+    w = WORKLOADS[name]
+    x, v, m = make_state(name)
+    S = w.steps
+    # the FP64 reference trajectory, parity-checked at both ends
+    xd, vd, md = to_dev(x, v, m, "f64")
+    e0 = _f64_force_parity(xd, md, w.eps, name, seed=61)
+    D0 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec="f64"))
+    acc = torch.empty_like(xd)
+    nb.step(xd, vd, md, acc, w.eps, w.dt, S, prec="f64")
+    D1 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec="f64"))
+    e1 = _f64_force_parity(xd, md, w.eps, name, seed=62)
+    print("%s FP64 reference: force parity %.3g (step 0), %.3g (step %d)" % (name, e0, e1, S))
+    assert e0 <= 1e-12 and e1 <= 1e-12
+    dE_ref = (D1["E"] - D0["E"]) / abs(D0["E"])
+    x_ref = host(xd)
+    travelled = np.linalg.norm(x_ref - x)
+    del xd, vd, acc
+    # the bound on the energy difference a 1e-5 force error allows
+    import oracle
+    idx = np.arange(0, x.shape[1], max(1, x.shape[1] // 8192))
+    a0 = oracle.accel_sampled(x, m, w.eps, idx)
+    power = float((m[idx] * np.linalg.norm(v[:, idx], axis=0) * np.linalg.norm(a0, axis=0)).sum()
+                  * (x.shape[1] / idx.size))
+    bound = 2.0 * 1e-5 * S * w.dt * power / abs(D0["E"])
+    for prec in w.precisions:
+        xd, vd, md = to_dev(x, v, m, prec)
+        acc = torch.empty_like(xd)
+        E0 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec=prec))["E"]
+        nb.step(xd, vd, md, acc, w.eps, w.dt, S, prec=prec)
+        E1 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec=prec))["E"]
+        assert E0 == pytest.approx(D0["E"], rel=1e-13)
+        dE = (E1 - E0) / abs(E0)
+        dx = np.linalg.norm(host(xd) - x_ref)
+        print("%s %s: dE %.4e (FP64 trajectory %.4e, difference %.3g, bound %.3g); "
+              "|x - x_fp64| %.3g of the distance travelled"
+              % (name, prec, dE, dE_ref, abs(dE - dE_ref), bound, dx / travelled))
+        assert abs(dE - dE_ref) <= bound
+        assert dx <= 1e-5 * travelled
+        del xd, vd, acc

@@ -75,12 +75,26 @@ def test_noalloc_separate_sets():
         assert rel(host(got[0]), r) <= 1e-5
 
 
-def test_noalloc_refuses_passes_beyond_its_scratch():
-    """262144 particles on themselves need ~805 MB of partials in the
-    symmetric pass: more than the 128 MiB array, so NB_EWORKSPACE, and the
-    output is left untouched."""
-    n, prec = 262144, "mix_tilec"
+def test_noalloc_bands_within_its_scratch():
+    """262144 particles on themselves: 805 MB of partials in the symmetric
+    pass, which nbody_accel runs in one band; the no-alloc entry point runs
+    it in bands within its 128 MiB, bitwise the same."""
+    n, prec, eps = 262144, "mix_tilec", 2.0 ** -9
     assert nb.pass_info(1, n, prec)["workspace_bytes"] > (128 << 20)
+    x, v, m = plummer_sphere(n, 33)
+    xd, _, md = to_dev(x, v, m, prec)
+    for _ in range(2):
+        got = _noalloc(xd, md, eps, prec)
+        assert torch.equal(got, nb.accel(xd, md, eps, prec=prec))
+    idx = np.arange(0, n, n // 256)
+    assert rel(host(got)[:, idx], oracle.accel_sampled(host(xd), host(md), eps, idx)) <= 1e-5
+
+
+def test_noalloc_refuses_passes_beyond_its_scratch():
+    """3 x 2^20 particles on themselves: the running sums and one block row
+    of the banded symmetric pass need ~151 MB, more than the 128 MiB array,
+    so NB_EWORKSPACE, and the output is left untouched."""
+    n, prec = 3 << 20, "mix_tilec"
     x = torch.zeros((3, n), dtype=torch.float64, device=DEV)
     m = torch.zeros(n, dtype=torch.float32, device=DEV)
     acc = torch.full_like(x, 7.0)
