@@ -6,10 +6,13 @@ dt = 2^-11, FP32 pair arithmetic with tile-compensated FP64 sums, FP64
 positions and drift; R = 10 by default):
   * FP64 energy / momentum diagnostics of the initial state;
   * the forward rollout: a(x_0), then R KDK steps (R+1 force evaluations),
-    with the state checkpointed every 20 steps;
+    with the state (x, v, a) checkpointed every K steps -- by default every
+    step, when the checkpoints fit in a quarter of the free HBM (0.8 GB at
+    2^20 for R = 10);
   * FP64 diagnostics of the final state;
   * the adjoint walk back over the R steps from the final state (R+1 fused
-    adjoint pair passes, each also giving a(x) for the walk-back).
+    adjoint pair passes; a state the forward pass checkpointed is reloaded,
+    any other is walked back, its force recomputed in the pass).
 Inputs are resident in HBM before timing starts. `value` counts pair
 interactions of the force and adjoint kernels, N^2 per pass, per second of
 the whole step. Per-kernel device times come from the library's own HIP
@@ -83,6 +86,20 @@ def executed_flop(kind, n, info, force_sums=True):
     return off * sym_f + one * one_f
 
 
+def checkpoint_interval(arg, R, n, pos_bytes):
+    """The rollout's checkpoint interval: `arg` if it is an integer, else
+    (auto) the smallest K >= 1 whose R // K + 1 slots of 9 n position-type
+    values fit in a quarter of the free device memory."""
+    if str(arg) != "auto":
+        return max(1, int(arg))
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    for K in range(1, max(1, R) + 1):
+        if (R // K + 1) * 9 * n * pos_bytes <= free // 4:
+            return K
+    return max(1, R)
+
+
 def adjoint_schedule(R, K):
     """(passes with the force sums, passes without) of the reverse walk of an
     R-step rollout checkpointed every K steps, started with the entry-half
@@ -99,15 +116,24 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="scale-2^20")
     ap.add_argument("--rollout", type=int, default=10, help="KDK steps per forward+adjoint pass")
-    ap.add_argument("--ckpt-every", type=int, default=20,
-                    help="checkpoint interval of the rollout (1: every step, so that every "
-                         "adjoint pass reloads its state instead of walking it back)")
+    ap.add_argument("--ckpt-every", default="auto",
+                    help="checkpoint interval of the rollout: an integer >= 1, or 'auto' (the "
+                         "default): every step when the checkpoints (72 bytes per particle per "
+                         "stored step in the mixed policies) fit in a quarter of the free device "
+                         "memory, so that the reverse walk reloads every state the forward pass "
+                         "computed instead of recomputing its force; else the smallest interval "
+                         "that fits")
     ap.add_argument("--prec", default="mix_tilec")
     ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="sinks in the CPU-oracle baseline sample (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one plain device-to-device copy of this many MiB (to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR",
+                                                         "COPY_WRITE_DIR"),
+                    help="no GPU: turn four rocprofv3 --pmc output folders (FETCH_SIZE and "
+                         "WRITE_SIZE of a run of this benchmark with --rollout R, and of "
+                         "--copy-probe-mib 1024) into profiles/hbm_traffic.json")
     return ap.parse_args()
 
 
@@ -274,6 +300,94 @@ def bench_diffusion(args):
     print(json.dumps(out), flush=True)
 
 
+# kernel families whose HBM traffic is summarised: the pair kernel and its
+# fold (finishing) kernel, per pass
+TRAFFIC_KERNELS = {"force_sym_kernel": ("force_sym_kernel", "force_sym_finish_kernel"),
+                   "adjoint_sym_kernel": ("adjoint_sym_kernel", "adjoint_sym_finish_kernel"),
+                   "force_kernel": ("force_kernel", "force_reduce_kernel"),
+                   "adjoint_kernel": ("adjoint_kernel", "adjoint_reduce_kernel")}
+
+
+def _kernel_base(name):
+    """The bare function name of a (demangled) kernel name: 'void
+    nb::(anonymous namespace)::adjoint_sym_kernel<8, 2, true>(...)' ->
+    'adjoint_sym_kernel'."""
+    import re
+    name = re.sub(r"^void\s+", "", name.strip()).replace("(anonymous namespace)::", "")
+    head = re.split(r"[<(]", name, maxsplit=1)[0]
+    return head.split("::")[-1].strip()
+
+
+def _pmc_rows(folder, counter):
+    """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV output
+    folder for one counter."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit("no %s rows under %s" % (counter, folder))
+    return rows
+
+
+def traffic_summary(args):
+    """profiles/hbm_traffic.json from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the same counter reads for a plain copy of
+    known size; bytes per pass = the pair kernel's and its fold kernel's
+    dispatches of the run over the passes of the run (R + 1 of each kind)."""
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = args.traffic_from
+    copy_bytes = 1 << 30
+    def copy_kib(folder, counter):
+        vals = [v for k, v in _pmc_rows(folder, counter) if "copy" in k.lower() or "elementwise" in k]
+        return max(vals)
+    f_factor = copy_bytes / (copy_kib(cfetch_dir, "FETCH_SIZE") * 1024.0)   # bytes read per KiB counted
+    w_factor = copy_bytes / (copy_kib(cwrite_dir, "WRITE_SIZE") * 1024.0)
+    fetch, write = _pmc_rows(fetch_dir, "FETCH_SIZE"), _pmc_rows(write_dir, "WRITE_SIZE")
+    passes = args.rollout + 1
+    out = {"_note": "HBM-side bytes per pass = (FETCH_SIZE KiB x 1024 x %.3f + WRITE_SIZE KiB x "
+                    "1024 x %.3f) summed over the pair kernel's and its fold kernel's dispatches "
+                    "of one benchmark step with --rollout %d, over its %d passes; factors from a "
+                    "plain 1 GiB device copy (the bytes it moves over the counters' reading); "
+                    "regenerate when the kernel's sources change" % (f_factor, w_factor,
+                                                                     args.rollout, passes),
+           "commands": ["cd /tmp && export TMPDIR=/tmp; from the repository root, one counter C "
+                        "per run, C in FETCH_SIZE WRITE_SIZE:",
+                        "rocprofv3 --pmc C -d gpurun_out/pmc_C -o bench --output-format csv -- "
+                        "python3 bench.py --steps 1 --warmup 0 --rollout %d --cpu-sample 0" % args.rollout,
+                        "rocprofv3 --pmc C -d gpurun_out/pmc_copy_C -o copy --output-format csv -- "
+                        "python3 bench.py --copy-probe-mib 1024",
+                        "python3 bench.py --rollout %d --traffic-from gpurun_out/pmc_FETCH_SIZE "
+                        "gpurun_out/pmc_WRITE_SIZE gpurun_out/pmc_copy_FETCH_SIZE "
+                        "gpurun_out/pmc_copy_WRITE_SIZE" % args.rollout]}
+    for fam, names in TRAFFIC_KERNELS.items():
+        fk = sum(v for k, v in fetch if _kernel_base(k) in names)
+        wk = sum(v for k, v in write if _kernel_base(k) in names)
+        nd = sum(1 for k, _ in fetch if _kernel_base(k) == fam)
+        if nd == 0:
+            continue
+        out["%s@%s" % (fam, args.workload)] = {
+            "source_sha256": kernel_source_hash(fam),
+            "bytes_per_launch": (fk * 1024.0 * f_factor + wk * 1024.0 * w_factor) / passes,
+            "fetch_bytes_per_pass": fk * 1024.0 * f_factor / passes,
+            "write_bytes_per_pass": wk * 1024.0 * w_factor / passes,
+            "pair_kernel_dispatches": nd, "passes": passes}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    old = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            old = json.load(fh)
+    for k, v in old.items():  # keep the entries of other workloads
+        if "@" in k and k not in out and not k.endswith("@" + args.workload):
+            out[k] = v
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: v for k, v in out.items() if "@" in k}, indent=1))
+
+
 def copy_probe(mib):
     import torch
     nbytes = mib << 20
@@ -291,6 +405,9 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.traffic_from:
+        traffic_summary(args)
+        return
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib)
         return
@@ -306,13 +423,14 @@ def main():
     from paper_2411_18889_amd import _lib
 
     w = WORKLOADS[args.workload]
-    prec, R, K = args.prec, args.rollout, max(1, args.ckpt_every)
+    prec, R = args.prec, args.rollout
     dev = torch.device("cuda:0")
     print("device:", nb.device_info(), flush=True)
     t0 = time.time()
     x0, v0, m0 = make_state(w)
     n = x0.shape[1]
     pdt, mdt = nb.pos_dtype(prec), nb.mass_dtype(prec)
+    K = checkpoint_interval(args.ckpt_every, R, n, torch.tensor([], dtype=pdt).element_size())
     X0 = torch.tensor(x0, dtype=pdt, device=dev)
     V0 = torch.tensor(v0, dtype=pdt, device=dev)
     M = torch.tensor(m0, dtype=mdt, device=dev)

@@ -127,13 +127,31 @@ typedef enum nb_op {
                                   state by dt instead of h (set on every call
                                   that does not end at the rollout's step 0)  */
 
-/* Explicit launch shape for nbody_accel_ex(); 0 in a field = library choice. */
+/* Explicit launch shape for nbody_accel_ex() and nbody_step_adjoint_ex();
+ * 0 in a field = library choice.
+ *   symmetric = 0: the one-sided kernel (every sink sums every source)
+ *     i_per_lane  sinks per lane: 1, 2 or 4 (adjoint: 1 or 2)
+ *     block       threads per workgroup (= j-tile length): 64, 128, 256, 512
+ *                 or 1024 (adjoint: up to 512)
+ *     split       j-split: number of source ranges per sink, 1..256; partial
+ *                 sums are combined in a fixed order
+ *   symmetric = 1: the symmetric (third-law) pass of one set on itself
+ *                 (force: NB_MIX_TILEC, NB_F32, NB_F64; adjoint: NB_MIX_TILEC)
+ *     block       threads per workgroup, waves x 64; with i_per_lane sinks
+ *                 per lane, blocks of block x i_per_lane particles. Shapes
+ *                 (block, i_per_lane): force (128, 2), (256, 2), (512, 2),
+ *                 (1024, 2), (128, 4), (256, 4), (512, 4), (1024, 4);
+ *                 adjoint (128, 2), (256, 2), (512, 2), (1024, 2), (256, 1),
+ *                 (512, 1), (128, 4), (256, 4), (512, 4) (with four sinks per
+ *                 lane each sink's sum is an FP32 running sum over the source
+ *                 block, as the source side's always is)
+ *     split       must be 0 or 1
+ * Other shapes: NB_EUNSUPPORTED. */
 typedef struct nb_launch {
-    int32_t i_per_lane; /* sinks per lane: 1, 2 or 4                          */
-    int32_t block;      /* threads per workgroup (= j-tile length): 64..1024,
-                           a multiple of 64                                    */
-    int32_t split;      /* j-split: number of source ranges per sink, 1..256;
-                           partial sums are combined in a fixed order         */
+    int32_t i_per_lane;
+    int32_t block;
+    int32_t split;
+    int32_t symmetric;
 } nb_launch;
 
 /*
@@ -190,7 +208,8 @@ int nbody_accel_noalloc(int64_t ni, const void *xi, int64_t nj, const void *xj,
 /*
  * nbody_accel_ex -- nbody_accel with an explicit launch shape (for tuning and
  * for tests that a result does not depend on the shape). NULL launch = the
- * library's choice. NB_EUNSUPPORTED for a shape outside nb_launch's limits.
+ * library's choice. NB_EUNSUPPORTED for a shape outside nb_launch's limits,
+ * or a symmetric shape for separate sets or a policy without that pass.
  */
 int nbody_accel_ex(int64_t ni, const void *xi, int64_t nj, const void *xj,
                    const void *mj, double eps, double G, int prec, void *acc,
@@ -271,6 +290,20 @@ int nbody_step_adjoint(int64_t n, void *x, void *v, const void *m, void *acc,
                        void *stream);
 
 /*
+ * nbody_step_adjoint_ex -- nbody_step_adjoint with an explicit launch shape
+ * for its fused adjoint pair passes (tuning, shape-invariance tests); NULL
+ * launch = the library's choice. NB_EUNSUPPORTED as nbody_accel_ex. The
+ * workspace is that of the shape: nbody_pass_workspace_size(NB_OP_ADJOINT,
+ * n, n, prec, 1, 0, launch).
+ */
+int nbody_step_adjoint_ex(int64_t n, void *x, void *v, const void *m, void *acc,
+                          void *lam_x, void *lam_v, void *lam_m, double eps,
+                          double G, double dt, int64_t nsteps, int prec,
+                          unsigned flags, const void *ckpt, int64_t ckpt_every,
+                          int64_t step_end, const nb_launch *launch, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/*
  * nbody_diag -- FP64 conserved quantities of a state (any policy; FP32
  * inputs are promoted exactly). out (device, 13 doubles):
  *   0 KE = 1/2 sum m|v|^2       1 PE = -G sum_{i<j} m_i m_j / sqrt(s_ij)
@@ -317,12 +350,14 @@ int nbody_profile_end(nb_profile *out);
  * row (NB_EWORKSPACE), and uses no more than every partial at once. */
 size_t nbody_workspace_size(int op, int64_t n, int prec);
 
-/* The workspace bytes one nbody_accel call (launch == NULL) or
- * nbody_accel_ex call (launch != NULL) asks for: ni sinks, nj sources,
- * self_set nonzero when xi == xj (then ni == nj), potential nonzero when pot
- * is given. 0 when none is needed or the arguments are invalid. */
-size_t nbody_accel_workspace_size(int64_t ni, int64_t nj, int prec, int self_set, int potential,
-                                  const nb_launch *launch);
+/* The workspace bytes one call asks for. op NB_OP_ACCEL: nbody_accel
+ * (launch == NULL) or nbody_accel_ex with ni sinks, nj sources, self_set
+ * nonzero when xi == xj (then ni == nj), potential nonzero when pot is given.
+ * op NB_OP_ADJOINT: nbody_step_adjoint(_ex) of ni == nj particles (self_set
+ * and potential ignored). 0 when none is needed or the arguments are
+ * invalid. */
+size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int self_set,
+                                 int potential, const nb_launch *launch);
 
 /*
  * nbody_pass_info -- the pair pass the library runs for n particles acting

@@ -25,7 +25,7 @@ PREC = {"f64": 0, "f32": 1, "mix_acc32": 2, "mix_kahan": 3, "mix_acc64": 4, "mix
 
 class nb_launch(ctypes.Structure):
     _fields_ = [("i_per_lane", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("split", ctypes.c_int32)]
+                ("split", ctypes.c_int32), ("symmetric", ctypes.c_int32)]
 
 
 class nb_pass_info(ctypes.Structure):
@@ -65,11 +65,14 @@ def lib():
                              vp, sz, vp]
     L.nbody_step_adjoint.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, i64,
                                      i32, u32, vp, i64, i64, vp, sz, vp]
+    L.nbody_step_adjoint_ex.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, dbl, i64,
+                                        i32, u32, vp, i64, i64, ctypes.POINTER(nb_launch), vp,
+                                        sz, vp]
     L.nbody_diag.argtypes = [i64, vp, vp, vp, dbl, dbl, i32, vp, vp, sz, vp]
     L.nbody_workspace_size.argtypes = [i32, i64, i32]
     L.nbody_workspace_size.restype = sz
-    L.nbody_accel_workspace_size.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(nb_launch)]
-    L.nbody_accel_workspace_size.restype = sz
+    L.nbody_pass_workspace_size.argtypes = [i32, i64, i64, i32, i32, i32, ctypes.POINTER(nb_launch)]
+    L.nbody_pass_workspace_size.restype = sz
     L.nbody_strerror.argtypes = [i32]
     L.nbody_strerror.restype = ctypes.c_char_p
     L.nbody_last_hip_error.argtypes = []
@@ -81,6 +84,7 @@ def lib():
     L.nbody_graph_cache_clear.argtypes = []
     L.nbody_pass_info.argtypes = [i32, i64, i32, ctypes.POINTER(nb_pass_info)]
     for f in ("nbody_accel", "nbody_accel_noalloc", "nbody_accel_ex", "nbody_step", "nbody_step_adjoint",
+              "nbody_step_adjoint_ex",
               "nbody_diag", "nbody_last_hip_error", "nbody_device_info",
               "nbody_profile_begin", "nbody_profile_end", "nbody_graph_cache_clear",
               "nbody_pass_info"):

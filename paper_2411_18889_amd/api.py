@@ -68,6 +68,17 @@ def _user_workspace(workspace):
     return ctypes.c_void_p(workspace.data_ptr() if workspace.numel() else 0), workspace.numel()
 
 
+def _launch(launch):
+    """An nb_launch from a dict with any of the keys i_per_lane, block, split,
+    symmetric (missing = 0 = the library's choice), or None."""
+    if launch is None:
+        return None
+    bad = set(launch) - {"i_per_lane", "block", "split", "symmetric"}
+    if bad:
+        raise ValueError("unknown launch fields %s" % sorted(bad))
+    return nb_launch(*[int(launch.get(k, 0)) for k in ("i_per_lane", "block", "split", "symmetric")])
+
+
 def accel(x, m, eps, G=1.0, prec="mix_tilec", xj=None, potential=False, launch=None,
           out=None, stream=None, workspace=None):
     """a (3, ni) of the sinks x (3, ni) from the sources xj (3, nj) with masses m
@@ -88,14 +99,13 @@ def accel(x, m, eps, G=1.0, prec="mix_tilec", xj=None, potential=False, launch=N
     pot = torch.empty(ni, dtype=pdt, device=x.device) if potential else None
     pp = _vec(pot, "pot", ni, pdt, rows=0) if potential else ctypes.c_void_p(0)
     L = _lib.lib()
-    ln = None
-    if launch is not None:
-        ln = nb_launch(*[int(launch.get(k, 0)) for k in ("i_per_lane", "block", "split")])
+    ln = _launch(launch)
     if workspace is not None:
         pws, nws = _user_workspace(workspace)
     else:
-        nws = int(L.nbody_accel_workspace_size(ni, nj, p, int(xj is None), int(bool(potential)),
-                                               None if ln is None else ctypes.byref(ln)))
+        nws = int(L.nbody_pass_workspace_size(_lib.NB_OP_ACCEL, ni, nj, p, int(xj is None),
+                                              int(bool(potential)),
+                                              None if ln is None else ctypes.byref(ln)))
         ws = torch.empty(nws, dtype=torch.uint8, device=x.device) if nws else None
         pws = ctypes.c_void_p(ws.data_ptr() if nws else 0)
     if ln is None:
@@ -138,10 +148,11 @@ def step(x, v, m, acc, eps, dt, nsteps, G=1.0, prec="mix_tilec", acc_valid=False
 
 def step_adjoint(x, v, m, acc, lam_x, lam_v, lam_m, eps, dt, nsteps, G=1.0,
                  prec="mix_tilec", entry_half=False, exit_full=False, ckpt=None,
-                 ckpt_every=0, step_end=0, stream=None, workspace=None):
+                 ckpt_every=0, step_end=0, stream=None, workspace=None, launch=None):
     """Walk nsteps KDK steps back from (x, v, acc), updating the adjoints
     lam_x, lam_v (3, n) and lam_m (n, float64) in place. workspace: as
-    accel."""
+    accel; launch: an explicit shape of the fused adjoint passes (as
+    accel's)."""
     p = _prec(prec)
     pdt, mdt = pos_dtype(prec), mass_dtype(prec)
     n = x.shape[1]
@@ -154,13 +165,23 @@ def step_adjoint(x, v, m, acc, lam_x, lam_v, lam_m, eps, dt, nsteps, G=1.0,
     else:
         pc = ctypes.c_void_p(0)
     flags = (_lib.NB_ADJ_ENTRY_HALF if entry_half else 0) | (_lib.NB_ADJ_EXIT_FULL if exit_full else 0)
+    L = _lib.lib()
+    ln = _launch(launch)
     if workspace is not None:
         pws, nws = _user_workspace(workspace)
-    else:
+    elif ln is None:
         ws, pws, nws = _workspace(_lib.NB_OP_ADJOINT, n, prec, x.device)
-    st = _lib.lib().nbody_step_adjoint(n, *args, float(eps), float(G), float(dt), int(nsteps),
-                                       p, flags, pc, int(ckpt_every), int(step_end), pws, nws,
-                                       _stream(stream))
+    else:
+        nws = int(L.nbody_pass_workspace_size(_lib.NB_OP_ADJOINT, n, n, p, 1, 0, ctypes.byref(ln)))
+        ws = torch.empty(nws, dtype=torch.uint8, device=x.device) if nws else None
+        pws = ctypes.c_void_p(ws.data_ptr() if nws else 0)
+    if ln is None:
+        st = L.nbody_step_adjoint(n, *args, float(eps), float(G), float(dt), int(nsteps), p, flags,
+                                  pc, int(ckpt_every), int(step_end), pws, nws, _stream(stream))
+    else:
+        st = L.nbody_step_adjoint_ex(n, *args, float(eps), float(G), float(dt), int(nsteps), p,
+                                     flags, pc, int(ckpt_every), int(step_end), ctypes.byref(ln),
+                                     pws, nws, _stream(stream))
     check(st, "nbody_step_adjoint")
 
 

@@ -274,6 +274,11 @@ Shape choose_adjoint_shape(int prec, int64_t n) {
     return s;
 }
 
+bool adjoint_shape_supported(const Shape& s) {
+    const bool bs_ok = s.block == 64 || s.block == 128 || s.block == 256 || s.block == 512;
+    return bs_ok && (s.ipl == 1 || s.ipl == 2) && s.split >= 1 && s.split <= 256;
+}
+
 size_t adjoint_partials_bytes(const Shape& s, int64_t n) {
     return (size_t)s.split * NQ * (size_t)n * sizeof(double);
 }

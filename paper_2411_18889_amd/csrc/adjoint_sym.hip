@@ -72,11 +72,11 @@ template <bool F> struct QRange {
     static constexpr int n = NQ - lo;     // partial rows per block
 };
 
-template <int K, bool JSIDE, bool F>
+template <int K, bool JSIDE, bool F, class Sum>
 __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 (*rl)[128], float* jq,
                                           const float* xi, const float* yi, const float* zi,
                                           const float* mi, const float* lxi, const float* lyi,
-                                          const float* lzi, SumTile (*s)[NQ], float eps2,
+                                          const float* lzi, Sum (*s)[NQ], float eps2,
                                           int lane) {
     // groups of 64 sources stored twice in a row: lane l reads source
     // (l + t) mod 64 at rp[g][l + t] (see the force pass)
@@ -191,7 +191,11 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         sink_block_origin<W>(cx, cy, cz, min(a.n - I * BI, BI), org, ox, oy, oz);
     }
     float xi[K], yi[K], zi[K], mi[K], lxi[K], lyi[K], lzi[K];
-    SumTile s[K][NQ];
+    // the sink side: with two sinks per lane an FP32 sum per 64-source group
+    // folded into FP64; with four (registers are short) an FP32 running sum
+    // over the block, as the source side is
+    using Sum = typename std::conditional<(K <= 2), SumTile, SumPlain<float>>::type;
+    Sum s[K][NQ];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
@@ -226,10 +230,11 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         }
         __syncthreads();
         if (jside)
-            asym_tile<K, true, F>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, lxi, lyi, lzi, s,
+            asym_tile<K, true, F, Sum>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, lxi, lyi, lzi, s,
                                   a.eps2, lane);
         else
-            asym_tile<K, false, F>(rp, rl, nullptr, xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2, lane);
+            asym_tile<K, false, F, Sum>(rp, rl, nullptr, xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2,
+                                        lane);
         __syncthreads();
         if (jside) {
             for (int q = tid; q < NQF * TJ; q += NT) {
@@ -336,6 +341,13 @@ constexpr size_t kAdjSymGrowBytes = size_t(32) << 30;
 
 }  // namespace
 
+bool adjoint_sym_shape_supported(int prec, const SymShape& s) {
+    if (prec != NB_MIX_TILEC) return false;
+    return (s.ipl == 2 && (s.waves == 2 || s.waves == 4 || s.waves == 8 || s.waves == 16)) ||
+           (s.ipl == 1 && (s.waves == 4 || s.waves == 8)) ||
+           (s.ipl == 4 && (s.waves == 2 || s.waves == 4 || s.waves == 8));
+}
+
 SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums) {
     const int64_t bi = (int64_t)s.waves * 64 * s.ipl;
     return SymLayout{n, bi, (int)((n + bi - 1) / bi), force_sums ? QRange<true>::n : QRange<false>::n,
@@ -424,6 +436,7 @@ hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, cons
 #define NB_ASYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_asym<WV, KV>(a, update_state, stream);
         NB_ASYM_CASE(2, 2) NB_ASYM_CASE(4, 2) NB_ASYM_CASE(8, 2) NB_ASYM_CASE(16, 2)
+        NB_ASYM_CASE(4, 1) NB_ASYM_CASE(8, 1) NB_ASYM_CASE(2, 4) NB_ASYM_CASE(4, 4) NB_ASYM_CASE(8, 4)
 #undef NB_ASYM_CASE
         if (e != hipSuccess) return e;
         f.first = I0 == 0;

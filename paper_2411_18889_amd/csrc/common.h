@@ -224,7 +224,9 @@ struct Shape {
 // Library choice of shape for ni sinks, nj sources.
 Shape choose_force_shape(int prec, int64_t ni, int64_t nj);
 Shape choose_adjoint_shape(int prec, int64_t n);
+// Shapes the one-sided force / adjoint kernels are built for.
 bool shape_supported(const Shape& s);
+bool adjoint_shape_supported(const Shape& s);
 
 // Workspace bytes of the split partials of a force / adjoint launch.
 size_t force_partials_bytes(const Shape& s, int64_t ni);
@@ -399,6 +401,8 @@ inline SymBandView sym_band_view(const SymLayout& L, int I0, int I1) {
 }
 
 SymShape choose_sym_shape(int prec, int64_t n, bool pot = false);
+// Shapes the symmetric force pass is built for (and policies that have it).
+bool sym_shape_supported(int prec, const SymShape& s);
 // The band layout of the symmetric force pass.
 SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot = false);
 // acc = a(x) (and with kick_v, v <- v + kick_h * acc; with pot, the
@@ -435,6 +439,7 @@ hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x
 // force_sums: the layout of a pass that also sums a(x) (seven quantities;
 // four without), which update_state asks for.
 SymShape choose_adjoint_sym_shape(int prec, int64_t n);
+bool adjoint_sym_shape_supported(int prec, const SymShape& s);
 SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums);
 hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
                               const void* lam_v, double eps, double G, double c,

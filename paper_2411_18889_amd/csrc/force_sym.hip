@@ -431,7 +431,8 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
         hipError_t e = hipErrorInvalidValue;
 #define NB_SYM_CASE(WV, KV) \
     if (sh.waves == WV && sh.ipl == KV) e = launch_sym<Pol, WV, KV>(a, pot != nullptr, stream);
-        NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+        NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(8, 2) NB_SYM_CASE(16, 2)
+        NB_SYM_CASE(2, 4) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
 #undef NB_SYM_CASE
         if (e != hipSuccess) return e;
         f.first = I0 == 0;
@@ -451,6 +452,11 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
 constexpr size_t kSymGrowBytes = size_t(16) << 30;
 
 }  // namespace
+
+bool sym_shape_supported(int prec, const SymShape& s) {
+    if (prec != NB_MIX_TILEC && prec != NB_F32 && prec != NB_F64) return false;
+    return (s.ipl == 2 || s.ipl == 4) && (s.waves == 2 || s.waves == 4 || s.waves == 8 || s.waves == 16);
+}
 
 SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
     const int64_t bi = (int64_t)s.waves * 64 * s.ipl;

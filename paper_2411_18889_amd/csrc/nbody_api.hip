@@ -214,6 +214,65 @@ hipError_t graph_launch(const StepKey& key, hipStream_t s, F&& enqueue) {
     return e;
 }
 
+// The symmetric shape a launch asks for: both fields given, or both 0 for
+// the library's choice (which must then be the symmetric pass).
+int sym_from_launch(const nb_launch& l, SymShape lib, SymShape* out) {
+    if (l.split > 1) return NB_EUNSUPPORTED;
+    if (l.block == 0 && l.i_per_lane == 0) {
+        if (!lib.waves) return NB_EUNSUPPORTED;
+        *out = lib;
+        return NB_OK;
+    }
+    if (l.block <= 0 || l.block % 64 != 0) return NB_EUNSUPPORTED;
+    *out = SymShape{l.block / 64, l.i_per_lane};
+    return NB_OK;
+}
+
+// The pass and shape of a force call: the symmetric pass for one set on
+// itself where the policy has one and no launch overrides it; else the
+// one-sided kernel in the library's shape with the launch's fields.
+int resolve_accel(int prec, int64_t ni, int64_t nj, bool self_set, bool pot,
+                  const nb_launch* launch, SymShape* sym, Shape* sh) {
+    *sym = (self_set && !launch) ? choose_sym_shape(prec, ni, pot) : SymShape{0, 0};
+    *sh = choose_force_shape(prec, ni, nj);
+    if (!launch) return NB_OK;
+    if (launch->symmetric) {
+        if (!self_set) return NB_EUNSUPPORTED;
+        const int st = sym_from_launch(*launch, choose_sym_shape(prec, ni, pot), sym);
+        if (st != NB_OK) return st;
+        return sym_shape_supported(prec, *sym) ? NB_OK : NB_EUNSUPPORTED;
+    }
+    if (launch->i_per_lane) sh->ipl = launch->i_per_lane;
+    if (launch->block) sh->block = launch->block;
+    if (launch->split) sh->split = launch->split;
+    return shape_supported(*sh) ? NB_OK : NB_EUNSUPPORTED;
+}
+
+// The same for the fused adjoint pass of n particles.
+int resolve_adjoint(int prec, int64_t n, const nb_launch* launch, SymShape* sym, Shape* sh) {
+    *sym = choose_adjoint_sym_shape(prec, n);
+    *sh = choose_adjoint_shape(prec, n);
+    if (!launch) return NB_OK;
+    if (launch->symmetric) {
+        const int st = sym_from_launch(*launch, *sym, sym);
+        if (st != NB_OK) return st;
+        return adjoint_sym_shape_supported(prec, *sym) ? NB_OK : NB_EUNSUPPORTED;
+    }
+    *sym = SymShape{0, 0};
+    if (launch->i_per_lane) sh->ipl = launch->i_per_lane;
+    if (launch->block) sh->block = launch->block;
+    if (launch->split) sh->split = launch->split;
+    return adjoint_shape_supported(*sh) ? NB_OK : NB_EUNSUPPORTED;
+}
+
+size_t adjoint_partials_need(const SymShape& sym, const Shape& sh, int64_t n, bool least) {
+    if (sym.waves) {
+        const SymLayout L = adjoint_sym_layout(sym, n, true);
+        return least ? sym_min_bytes(L) : sym_default_bytes(L);
+    }
+    return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
+}
+
 }  // namespace
 
 namespace nb {
@@ -240,16 +299,9 @@ int accel_plan(int64_t ni, const void* xi, int64_t nj, const void* xj, const voi
                 overlaps(pot, (size_t)ni * ps, xj, 3 * (size_t)nj * ps) ||
                 overlaps(pot, (size_t)ni * ps, mj, (size_t)nj * ms)))
         return NB_EINVAL;
-    // one set on itself, library shape: the symmetric pass where the policy
-    // has one
-    plan->sym = (self_set && !launch) ? choose_sym_shape(prec, ni, pot != nullptr) : SymShape{0, 0};
-    Shape sh = choose_force_shape(prec, ni, nj);
-    if (launch) {
-        if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
-        if (launch->block) sh.block = launch->block;
-        if (launch->split) sh.split = launch->split;
-        if (!shape_supported(sh)) return NB_EUNSUPPORTED;
-    }
+    Shape sh;
+    const int st = resolve_accel(prec, ni, nj, self_set, pot != nullptr, launch, &plan->sym, &sh);
+    if (st != NB_OK) return st;
     plan->sh = sh;
     plan->self_set = self_set;
     if (plan->sym.waves) {
@@ -449,10 +501,15 @@ int nbody_graph_cache_clear(void) {
     return hip_status(err);
 }
 
-int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, void* lam_x,
-                       void* lam_v, void* lam_m, double eps, double G, double dt, int64_t nsteps,
-                       int prec, unsigned flags, const void* ckpt, int64_t ckpt_every,
-                       int64_t step_end, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int adjoint_common(int64_t n, void* x, void* v, const void* m, void* acc, void* lam_x,
+                   void* lam_v, void* lam_m, double eps, double G, double dt, int64_t nsteps,
+                   int prec, unsigned flags, const void* ckpt, int64_t ckpt_every,
+                   int64_t step_end, const nb_launch* launch, void* ws, size_t ws_bytes,
+                   void* stream) {
     if (!valid_prec(prec)) return NB_EUNSUPPORTED;
     if (n < 1 || n > kMaxN || nsteps < 0) return NB_EINVAL;
     if (!valid_eps(eps, prec) || !isfinite(G) || !isfinite(dt)) return NB_EINVAL;
@@ -477,11 +534,12 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
         for (int p = 0; p < 6; ++p)
             if (overlaps(ckpt, cb, bufs[p], sizes[p])) return NB_EINVAL;
     }
-    const Shape sh = choose_adjoint_shape(prec, n);
-    const SymShape sym = choose_adjoint_sym_shape(prec, n);
-    const size_t need = sym.waves ? sym_min_bytes(adjoint_sym_layout(sym, n, true))
-                                  : (sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0);
-    int st = check_ws(ws, ws_bytes, need);
+    Shape sh;
+    SymShape sym;
+    int st = resolve_adjoint(prec, n, launch, &sym, &sh);
+    if (st != NB_OK) return st;
+    const size_t need = adjoint_partials_need(sym, sh, n, true);
+    st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
     const size_t used = sym.waves ? std::min(ws_bytes, sym_full_bytes(adjoint_sym_layout(sym, n, true)))
                                   : need;
@@ -545,6 +603,27 @@ int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, vo
     return hip_status(e);
 }
 
+}  // namespace
+
+extern "C" {
+
+int nbody_step_adjoint(int64_t n, void* x, void* v, const void* m, void* acc, void* lam_x,
+                       void* lam_v, void* lam_m, double eps, double G, double dt, int64_t nsteps,
+                       int prec, unsigned flags, const void* ckpt, int64_t ckpt_every,
+                       int64_t step_end, void* ws, size_t ws_bytes, void* stream) {
+    return adjoint_common(n, x, v, m, acc, lam_x, lam_v, lam_m, eps, G, dt, nsteps, prec, flags,
+                          ckpt, ckpt_every, step_end, nullptr, ws, ws_bytes, stream);
+}
+
+int nbody_step_adjoint_ex(int64_t n, void* x, void* v, const void* m, void* acc, void* lam_x,
+                          void* lam_v, void* lam_m, double eps, double G, double dt,
+                          int64_t nsteps, int prec, unsigned flags, const void* ckpt,
+                          int64_t ckpt_every, int64_t step_end, const nb_launch* launch,
+                          void* ws, size_t ws_bytes, void* stream) {
+    return adjoint_common(n, x, v, m, acc, lam_x, lam_v, lam_m, eps, G, dt, nsteps, prec, flags,
+                          ckpt, ckpt_every, step_end, launch, ws, ws_bytes, stream);
+}
+
 int nbody_diag(int64_t n, const void* x, const void* v, const void* m, double eps, double G,
                int prec, double* out, void* ws, size_t ws_bytes, void* stream) {
     if (!valid_prec(prec)) return NB_EUNSUPPORTED;
@@ -582,20 +661,19 @@ int diffusion3d_step(int64_t nx, int64_t ny, int64_t nz, double dx, double dy, d
     }));
 }
 
-size_t nbody_accel_workspace_size(int64_t ni, int64_t nj, int prec, int self_set, int potential,
-                                  const nb_launch* launch) {
+size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int self_set,
+                                 int potential, const nb_launch* launch) {
     if (!valid_prec(prec) || ni < 1 || nj < 1 || ni > kMaxN || nj > kMaxN) return 0;
-    if (self_set && ni != nj) return 0;
-    const SymShape sym = (self_set && !launch) ? choose_sym_shape(prec, ni, potential != 0)
-                                               : SymShape{0, 0};
-    if (sym.waves) return sym_default_bytes(sym_layout(prec, sym, ni, potential != 0));
-    Shape sh = choose_force_shape(prec, ni, nj);
-    if (launch) {
-        if (launch->i_per_lane) sh.ipl = launch->i_per_lane;
-        if (launch->block) sh.block = launch->block;
-        if (launch->split) sh.split = launch->split;
-        if (!shape_supported(sh)) return 0;
+    SymShape sym;
+    Shape sh;
+    if (op == NB_OP_ADJOINT) {
+        if (ni != nj || resolve_adjoint(prec, ni, launch, &sym, &sh) != NB_OK) return 0;
+        return adjoint_partials_need(sym, sh, ni, false);
     }
+    if (op != NB_OP_ACCEL || (self_set && ni != nj)) return 0;
+    if (resolve_accel(prec, ni, nj, self_set != 0, potential != 0, launch, &sym, &sh) != NB_OK)
+        return 0;
+    if (sym.waves) return sym_default_bytes(sym_layout(prec, sym, ni, potential != 0));
     return accel_ws(sh, ni);
 }
 

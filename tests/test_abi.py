@@ -361,3 +361,56 @@ def test_workspace_overlap_rejected(L):
     out = P(9 * 64 * MiB)
     assert L.nbody_diag(n, x, v, m, 0.01, 1.0, TILEC, out, P(out.value - 256), wsd, None) == NB_EINVAL
     assert L.nbody_diag(n, x, v, m, 0.01, 1.0, TILEC, out, P(v.value + 256), wsd, None) == NB_EINVAL
+
+
+def test_explicit_pass_shapes_validated(L):
+    """Explicit launch shapes of the symmetric passes and of the one-sided
+    adjoint: shapes the library is not built for, a symmetric shape for
+    separate sets or for a policy without that pass, and a split of the
+    symmetric pass are refused (NB_EUNSUPPORTED) before any device call;
+    the workspace query answers per shape."""
+    MiB = 1 << 20
+    x, m, acc = P(64 * MiB), P(128 * MiB), P(192 * MiB)
+    xj = P(256 * MiB)
+
+    def ex(n, launch, prec=TILEC, src=None):
+        ln = nb_launch(*launch)
+        return L.nbody_accel_ex(n, x, n, src or x, m, 0.01, 1.0, prec, acc, None,
+                                ctypes.byref(ln), None, 0, None)
+    assert ex(20000, (4, 256, 1, 1), src=xj) == NB_EUNSUPPORTED   # separate sets
+    assert ex(20000, (4, 192, 0, 1)) == NB_EUNSUPPORTED           # not whole waves
+    assert ex(20000, (1, 256, 0, 1)) == NB_EUNSUPPORTED           # force: 2 or 4 per lane
+    assert ex(20000, (4, 2048, 0, 1)) == NB_EUNSUPPORTED          # at most 16 waves
+    assert ex(20000, (4, 256, 2, 1)) == NB_EUNSUPPORTED           # no split
+    assert ex(20000, (4, 256, 0, 1), prec=3) == NB_EUNSUPPORTED   # Kahan: no symmetric pass
+    assert ex(1000, (0, 0, 0, 1)) == NB_EUNSUPPORTED              # library picks one-sided there
+
+    def adj(launch, prec=TILEC, n=20000):
+        ln = nb_launch(*launch)
+        lx, lv, lm, v = P(320 * MiB), P(384 * MiB), P(448 * MiB), P(512 * MiB)
+        return L.nbody_step_adjoint_ex(n, x, v, m, acc, lx, lv, lm, 0.01, 1.0, 0.01, 1, prec, 0,
+                                       None, 0, 0, ctypes.byref(ln), None, 0, None)
+    assert adj((2, 256, 0, 1), prec=F64) == NB_EUNSUPPORTED       # FP64: one-sided only
+    assert adj((3, 256, 0, 1)) == NB_EUNSUPPORTED                 # adjoint: 1, 2 or 4 per lane
+    assert adj((4, 1024, 0, 1)) == NB_EUNSUPPORTED                # 4 per lane: up to 8 waves
+    assert adj((1, 128, 0, 1)) == NB_EUNSUPPORTED                 # 1 per lane: 4 or 8 waves
+    assert adj((1, 1024, 1, 0)) == NB_EUNSUPPORTED                # one-sided: up to 512 lanes
+    assert adj((4, 256, 1, 0)) == NB_EUNSUPPORTED
+    # the workspace a shape asks for: symmetric partials (every one up to
+    # 4 GiB), or one-sided FP64 split partials
+    q = L.nbody_pass_workspace_size
+    ln = nb_launch(2, 256, 0, 1)   # blocks of 512
+    assert q(0, 20000, 20000, TILEC, 1, 0, ctypes.byref(ln)) == 40 * 3 * 20000 * 4
+    assert q(0, 20000, 20000, TILEC, 1, 1, ctypes.byref(ln)) == 40 * 4 * 20000 * 4
+    assert q(0, 20000, 20000, F32, 1, 0, ctypes.byref(ln)) == 40 * 3 * 20000 * 4
+    assert q(0, 20000, 20000, F64, 1, 0, ctypes.byref(ln)) == 40 * 3 * 20000 * 8
+    assert q(0, 20000, 20000, TILEC, 0, 0, ctypes.byref(ln)) == 0  # separate sets: refused
+    assert q(2, 20000, 20000, TILEC, 1, 0, ctypes.byref(ln)) == 40 * 7 * 20000 * 4
+    ln = nb_launch(1, 256, 5, 0)
+    assert q(2, 20000, 20000, F64, 1, 0, ctypes.byref(ln)) == 5 * 7 * 20000 * 8
+    assert q(0, 20000, 700, TILEC, 0, 0, ctypes.byref(ln)) == 5 * 4 * 20000 * 8
+    assert q(2, 20000, 20001, TILEC, 1, 0, None) == 0
+    assert q(1, 20000, 20000, TILEC, 1, 0, None) == 0              # op: ACCEL or ADJOINT
+    # the library's own shapes agree with nbody_workspace_size
+    assert q(2, 1 << 20, 1 << 20, TILEC, 1, 0, None) == L.nbody_workspace_size(2, 1 << 20, TILEC)
+    assert q(0, 1 << 20, 1 << 20, TILEC, 1, 0, None) == L.nbody_workspace_size(1, 1 << 20, TILEC)

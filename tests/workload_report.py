@@ -1,0 +1,287 @@
+"""Per-workload report of the MI355X results: throughput, accuracy against
+the FP64 oracle, energy drift, the adjoint's cost and gradient error, pass
+times across N and the oracle's own CPU rate -- every figure of the result
+tables, regenerated from committed code on one GPU.
+
+    python tests/workload_report.py [--only NAME ...] [--skip-scan] [--skip-cpu]
+
+Prints markdown on stdout (progress on stderr). Test infrastructure: it uses
+the oracle (oracle/) for the reference values, as the GPU tests do.
+
+Per workload and precision:
+  * force pass: best of 5 `nbody_accel` calls of the set on itself, resident
+    inputs, HIP events; Ginteractions/s = N^2 / time; % of the 157.3 TFLOP/s
+    FP32 (78.6 FP64) vector peak from executed flop (pair evaluations x
+    executed flop per evaluation) and, in brackets, by the paper's
+    convention of 20 flop per interaction;
+  * e_glob, per-particle p99 and max against the oracle on the same values:
+    every sink up to 65536 particles, else 4096 seeded sinks plus the 128
+    nearest the centre and (subcluster) the 128 nearest the subcluster's
+    centre;
+  * dE = (E_S - E_0) / |E_0| over the workload's steps (FP64 diagnostics),
+    beside the same for an FP64 trajectory on the GPU (the subcluster and
+    2^20 workloads) or for the oracle's own trajectory (1024: all steps;
+    65536: the stored oracle energies);
+  * adjoint-16384: forward rollout and backward times, gradient error
+    against the stored oracle gradient.
+"""
+
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from nbody_inputs import WORKLOADS, make_state, plummer_sphere  # noqa: E402
+
+FP32_PEAK, FP64_PEAK = 157.3e12, 78.6e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _bench():
+    sys.path.insert(0, ROOT)
+    import bench
+    return bench
+
+
+def timed(fn, reps=5):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def errors(a, ref):
+    e = float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+    pe = np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    return e, float(np.quantile(pe, 0.99)), float(pe.max())
+
+
+def sample(name, xs):
+    from tests.gpu_util import cluster_centres, sample_indices
+    n = xs.shape[1]
+    if n <= 65536:
+        return np.arange(n)
+    return sample_indices(xs, 4096, 128, seed=7, centres=cluster_centres(name, xs))
+
+
+def force_row(name, prec, x, v, m, w):
+    import torch
+    import paper_2411_18889_amd as nb
+    from tests.gpu_util import host, to_dev
+    bench = _bench()
+    n = x.shape[1]
+    xd, vd, md = to_dev(x, v, m, prec)
+    info = nb.pass_info(1, n, prec)
+    ms = timed(lambda: nb.accel(xd, md, w.eps, prec=prec))
+    flop = bench.executed_flop("force", n, info)
+    peak = FP64_PEAK if prec == "f64" else FP32_PEAK
+    a = host(nb.accel(xd, md, w.eps, prec=prec))
+    xs, ms_ = host(xd), host(md)
+    idx = sample(name, xs)
+    ref = oracle.accel_sampled(xs, ms_, w.eps, idx) if idx.size < n else oracle.accel(xs, ms_, w.eps)
+    e, p99, mx = errors(a[:, idx], ref)
+    # the workload's trajectory in this precision, FP64 diagnostics
+    acc = torch.empty_like(xd)
+    E0 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec=prec))["E"]
+    t0 = time.time()
+    nb.step(xd, vd, md, acc, w.eps, w.dt, w.steps, prec=prec)
+    torch.cuda.synchronize()
+    t_steps = time.time() - t0
+    E1 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec=prec))["E"]
+    return {"prec": prec, "pass": "symmetric %d" % info["block_particles"] if info["symmetric"]
+            else "one-sided %dx%d/%d" % (info["i_per_lane"], info["block"], info["split"]),
+            "ms": ms, "gint": n * n / ms / 1e6, "frac": flop / (ms * 1e-3) / peak,
+            "frac_conv": 20.0 * n * n / (ms * 1e-3) / peak,
+            "e": e, "p99": p99, "max": mx, "dE": (E1 - E0) / abs(E0), "steps_s": t_steps,
+            "x_end": host(xd)}
+
+
+def workload_rows(name):
+    import torch
+    import paper_2411_18889_amd as nb
+    from tests.gpu_util import host, to_dev
+    w = WORKLOADS[name]
+    x, v, m = make_state(name)
+    n = x.shape[1]
+    rows = [force_row(name, p, x, v, m, w) for p in w.precisions]
+    ref = ""
+    if name == "fp64-1024":
+        xo, vo, _ = oracle.kdk(x, v, m, w.eps, w.dt, w.steps)
+        D0, D1 = oracle.diag(x, v, m, w.eps), oracle.diag(xo, vo, m, w.eps)
+        ref = "oracle %.6e; positions after %d steps within %.2g of the oracle's" % (
+            (D1["E"] - D0["E"]) / abs(D0["E"]), w.steps,
+            np.linalg.norm(rows[0]["x_end"] - xo) / np.linalg.norm(xo))
+    elif name == "fp32-65536":
+        e = np.loadtxt(os.path.join(ROOT, "tests", "golden", "energy_65536.txt"))
+        ref = "oracle %.3e (stored FP64 run from the same FP32 state)" % ((e[-1, 1] - e[0, 1]) / abs(e[0, 1]))
+    elif name in ("subcluster-262144", "scale-2^20"):
+        xd, vd, md = to_dev(x, v, m, "f64")
+        acc = torch.empty_like(xd)
+        E0 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec="f64"))["E"]
+        nb.step(xd, vd, md, acc, w.eps, w.dt, w.steps, prec="f64")
+        E1 = nb.diag_dict(nb.diag(xd, vd, md, w.eps, prec="f64"))["E"]
+        xs = host(xd)
+        idx = sample(name, xs)[:512]
+        e64 = float(np.linalg.norm(host(acc)[:, idx] - oracle.accel_sampled(xs, host(md), w.eps, idx))
+                    / np.linalg.norm(oracle.accel_sampled(xs, host(md), w.eps, idx)))
+        x64 = xs
+        ref = "GPU FP64 trajectory %.4e (its force at step %d within %.1g of the oracle, 512 sinks)" % (
+            (E1 - E0) / abs(E0), w.steps, e64)
+        for r in rows:
+            r["dx"] = float(np.linalg.norm(r["x_end"] - x64) / np.linalg.norm(x64 - x))
+    return w, n, rows, ref
+
+
+def adjoint_row():
+    import torch
+    import paper_2411_18889_amd as nb
+    from tests.gpu_util import host, rel, to_dev
+    w = WORKLOADS["adjoint-16384"]
+    g = np.load(os.path.join(ROOT, "tests", "golden", "adjoint_16384.npz"))
+    x, v, m = make_state(w)
+    best = None
+    for _ in range(3):
+        xd, vd, md = to_dev(x, v, m, "mix_tilec")
+        for t in (xd, vd, md):
+            t.requires_grad_(True)
+        y = torch.tensor(g["y"], device=xd.device)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        xs, _ = nb.rollout(xd, vd, md, w.eps, w.dt, w.steps, ckpt_every=w.ckpt_every, prec="mix_tilec")
+        loss = ((xs - y) ** 2).sum() / x.shape[1]
+        e[1].record()
+        loss.backward()
+        e[2].record()
+        torch.cuda.synchronize()
+        f, b = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+        if best is None or f + b < best[0] + best[1]:
+            errs = [rel(host(t.grad), g["g" + k]) for k, t in (("x", xd), ("v", vd), ("m", md))]
+            best = (f, b, errs)
+    return best
+
+
+def pass_scan():
+    """Force and adjoint-step times across N, library shapes."""
+    import torch
+    import paper_2411_18889_amd as nb
+    bench = _bench()
+    out = []
+    for n in (1024, 4096, 16384, 65536, 262144, 1 << 20, 1 << 21):
+        x, v, m = plummer_sphere(n, 3)
+        row = {"n": n}
+        for prec in ("mix_tilec", "f32", "f64"):
+            if prec == "f64" and n > 262144:
+                continue
+            log("scan n=%d %s" % (n, prec))
+            pdt, mdt = nb.pos_dtype(prec), nb.mass_dtype(prec)
+            X = torch.tensor(x, dtype=pdt, device="cuda")
+            V = torch.tensor(v, dtype=pdt, device="cuda")
+            M = torch.tensor(m, dtype=mdt, device="cuda")
+            reps = 5 if n <= 262144 else 2
+            ms = timed(lambda: nb.accel(X, M, 2.0 ** -9, prec=prec), reps)
+            info = nb.pass_info(1, n, prec)
+            peak = FP64_PEAK if prec == "f64" else FP32_PEAK
+            row["force_" + prec] = (ms, bench.executed_flop("force", n, info) / (ms * 1e-3) / peak)
+            if prec in ("mix_tilec", "f64"):
+                acc = nb.accel(X, M, 2.0 ** -9, prec=prec)
+                lam = torch.ones_like(X)
+                st = {}
+
+                def one():
+                    st["l"] = (torch.zeros_like(lam), lam.clone(), torch.zeros(n, dtype=torch.float64, device="cuda"))
+                    nb.step_adjoint(X.clone(), V.clone(), M, acc.clone(), *st["l"], 2.0 ** -9, 2.0 ** -16,
+                                    1, prec=prec)
+                ms = timed(one, reps)
+                ainfo = nb.pass_info(2, n, prec)
+                row["adj_" + prec] = (ms, bench.executed_flop("adjoint", n, ainfo, True) / (ms * 1e-3) / peak)
+        out.append(row)
+    return out
+
+
+def cpu_table():
+    out = []
+    k0 = oracle.num_threads()
+    for n, sinks in ((1024, None), (16384, None), (65536, None), (262144, 512), (1 << 20, 256)):
+        x, _, m = plummer_sphere(n, 3)
+        row = {"n": n}
+        for threads in (1, k0):
+            oracle.set_num_threads(threads)
+            s = sinks if sinks else (n if threads > 1 or n <= 16384 else 1024)
+            idx = np.arange(s) * (n // s)
+            t0 = time.time()
+            oracle.accel_sampled(x, m, 2.0 ** -9, idx)
+            row[threads] = (s * float(n) / (time.time() - t0) / 1e9, s)
+        out.append(row)
+    oracle.set_num_threads(k0)
+    return out, k0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--only", nargs="*", default=list(WORKLOADS))
+    ap.add_argument("--skip-scan", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    import paper_2411_18889_amd as nb
+    print("Device: %s. Command: `python tests/workload_report.py%s`\n"
+          % (nb.device_info(), "".join(" " + a for a in sys.argv[1:])))
+    print("| workload | N | precision | pass | force pass | Ginteractions/s | % peak executed (20-flop convention) "
+          "| e_glob | p99 | max | dE over the steps | reference dE | positions vs FP64 run |")
+    print("|---|---:|---|---|---:|---:|---|---|---|---|---|---|---|")
+    for name in args.only:
+        if name == "adjoint-16384":
+            continue
+        log("workload", name)
+        w, n, rows, ref = workload_rows(name)
+        for r in rows:
+            print("| %s | %d | %s | %s | %.4g ms | %.0f | %.1f %% (%.1f %%) | %.2g | %.2g | %.2g | %.4e | %s | %s |"
+                  % (name, n, r["prec"], r["pass"], r["ms"], r["gint"], 100 * r["frac"],
+                     100 * r["frac_conv"], r["e"], r["p99"], r["max"], r["dE"], ref,
+                     "%.2g of the distance travelled" % r["dx"] if "dx" in r else "—"))
+    if "adjoint-16384" in args.only:
+        log("workload adjoint-16384")
+        f, b, errs = adjoint_row()
+        print("\nadjoint-16384 (200 steps, checkpoints every 20, mix_tilec): forward rollout %.1f ms, "
+              "backward %.1f ms, backward / forward %.2f; gradient rel err against the oracle "
+              "x0 %.2g, v0 %.2g, m %.2g" % (f, b, b / f, *errs))
+    if not args.skip_scan:
+        print("\nPass times across N (Plummer, eps = 2^-9; force = `nbody_accel` of the set on itself, "
+              "adjoint = one reverse step of `nbody_step_adjoint`; best of 5 (2 from 2^20); "
+              "% of the FP32 (FP64) vector peak from executed flop)\n")
+        print("| N | force tile-compensated | adjoint step tile-compensated | force FP32 | force FP64 | adjoint step FP64 |")
+        print("|---:|---|---|---|---|---|")
+        for r in pass_scan():
+            cell = lambda k: ("%.4g ms (%.0f %%)" % (r[k][0], 100 * r[k][1])) if k in r else "—"
+            print("| %d | %s | %s | %s | %s | %s |" % (r["n"], cell("force_mix_tilec"), cell("adj_mix_tilec"),
+                                                     cell("force_f32"), cell("force_f64"), cell("adj_f64")))
+    if not args.skip_cpu:
+        rows, k0 = cpu_table()
+        print("\nFP64 oracle (`oracle_accel`) on the host: Ginteractions/s (sampled sinks x all N)\n")
+        print("| N | 1 thread | %d threads |" % k0)
+        print("|---:|---|---|")
+        for r in rows:
+            print("| %d | %.3g (%d sinks) | %.3g (%d sinks) |" % (r["n"], r[1][0], r[1][1], r[k0][0], r[k0][1]))
+
+
+if __name__ == "__main__":
+    main()
