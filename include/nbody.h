@@ -95,7 +95,12 @@ typedef enum nb_status {
  *                 in FP32.
  *   NB_MIX_ACC64  as NB_MIX_ACC32, but each FP32 pair term is summed in FP64.
  *   NB_MIX_TILEC  as NB_MIX_ACC32, but the FP32 running sum restarts at every
- *                 j-tile and the tile sums are added in FP64.
+ *                 j-tile and the tile sums are added in FP64. In the
+ *                 symmetric passes the tiles are the source blocks (up to
+ *                 4096 particles): a particle's partial from one block is an
+ *                 FP32 sum (the force pass folds its sink side into FP64
+ *                 every 64 sources, as the adjoint does with two sinks per
+ *                 lane), and a particle's partials are added in FP64.
  */
 typedef enum nb_prec {
     NB_F64 = 0,

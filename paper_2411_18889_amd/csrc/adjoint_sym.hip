@@ -355,23 +355,32 @@ SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums) {
 }
 
 SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
-    // Measured on MI355X: two sinks per lane (the seven running sums per
-    // sink already take ~126 VGPRs; four take ~254 and halve the waves per
-    // SIMD) and blocks of 512 at N = 2^18; blocks are kept to at most n/64
-    // and grown, with more waves per workgroup (up to 2048 particles), while
-    // every FP32 partial of the pass at once (nb * 7 * n floats) would pass
-    // 32 GiB (blocks of 1024 at 2^20). The pass runs in bands when the
-    // workspace is smaller than that (SymLayout), so it serves every n up to
-    // 2^28.
+    // Measured on MI355X with the tuner (tune.py, one walked-back step):
+    //  * up to 2^18 particles two sinks per lane -- the seven running sums per
+    //    sink, each an FP32 group sum folded into FP64, take ~126 VGPRs --
+    //    in blocks of at most n/64 (256 or 512 particles; 65536: 4 waves x 2
+    //    the fastest, 2.12 ms);
+    //  * from 2^18 four sinks per lane with FP32 block sums on the sink side
+    //    (154 VGPRs, 3 waves per SIMD) in 4-wave blocks of 1024: half the LDS
+    //    reads and source-side rotations per pair, 4.3 % faster than 8 waves
+    //    x 2 at 2^20 (517 against 540 ms) and 4.5 % at 2^18 (32.3 against
+    //    33.9 ms);
+    //  * blocks grow, with more waves, while every FP32 partial of the pass at
+    //    once (nb * 7 * n floats) would pass 32 GiB; the pass runs in bands
+    //    when the workspace is smaller (SymLayout), so it serves every n up
+    //    to 2^28.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 31 % faster at 8192;
     // symmetric 12 % faster at 12288, 21 % at 24576).
     if (prec != NB_MIX_TILEC || n < 48 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
-    static const SymShape cands[] = {{2, 2}, {4, 2}, {8, 2}, {16, 2}};  // 256 .. 2048
-    constexpr int NC = 4;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
+    if (n < (int64_t(1) << 18)) {
+        static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
+        return (bi(small[1]) <= n / 64) ? small[1] : small[0];
+    }
+    static const SymShape cands[] = {{4, 4}, {8, 4}};  // 1024, 2048
+    constexpr int NC = 2;
     int k = 0;
-    while (k + 1 < NC && bi(cands[k + 1]) <= 512 && bi(cands[k + 1]) <= n / 64) ++k;
     while (k + 1 < NC && sym_full_bytes(adjoint_sym_layout(cands[k], n, true)) > kAdjSymGrowBytes) ++k;
     return cands[k];
 }

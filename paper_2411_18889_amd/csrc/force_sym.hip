@@ -466,10 +466,12 @@ SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
 }
 
 SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
-    // Measured on MI355X at N = 2^18 and 2^20: four-wave workgroups with four
-    // sinks per lane (blocks of 1024) are fastest -- more waves per SIMD than
-    // the larger workgroups, and one source rotation per four pairs. Blocks
-    // are kept to at most n/48 (>= 1176 equal work items for the 256 CUs),
+    // Measured on MI355X with the tuner (tune.py) from 16384 to 2^20: four-
+    // wave workgroups with four sinks per lane (blocks of 1024) are fastest
+    // from 2^17 particles -- more waves per SIMD than the larger workgroups,
+    // and one source rotation per four pairs; below, blocks of 512 (65536:
+    // 0.864 ms against 0.889 with 1024) and 256. Blocks are kept to at most
+    // n/48 (>= 1176 equal work items for the 256 CUs),
     // and grown (up to 4096) only while every FP32 partial of the pass at
     // once (nb * 3 * n floats, or nb * 4 * n with the potential) would pass
     // 16 GiB. The pass runs in bands when the workspace is smaller than that
@@ -484,7 +486,9 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     constexpr int NC = 5;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     int k = 0;
-    while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48) ++k;
+    while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48 &&
+           (bi(cands[k + 1]) < 1024 || n >= (int64_t(1) << 17)))
+        ++k;
     while (k + 1 < NC && sym_full_bytes(sym_layout(prec, cands[k], n, pot)) > kSymGrowBytes) ++k;
     return cands[k];
 }

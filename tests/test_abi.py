@@ -99,14 +99,14 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1 << 30, TILEC) == (1 << 24) * 4 * 8
     assert L.nbody_workspace_size(0, 1 << 30, F64) == (1 << 24) * 4 * 8
     # and the symmetric adjoint pass: seven FP32 partials per particle and
-    # block (blocks of min(n/64, 512), larger while every partial would pass
-    # 32 GiB, up to 2048), all of them up to 4 GiB, then seven FP64 running
-    # sums and bands of about 4 GiB
+    # block (blocks of min(n/64, 512) below 2^18, 1024 from there, larger
+    # while every partial would pass 32 GiB, up to 2048), all of them up to
+    # 4 GiB, then seven FP64 running sums and bands of about 4 GiB
     assert L.nbody_workspace_size(2, 12288, TILEC) == 48 * 7 * 12288 * 4
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
     assert L.nbody_workspace_size(2, 1 << 17, TILEC) == 256 * 7 * (1 << 17) * 4
-    assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 512 * 7 * (1 << 18) * 4
+    assert L.nbody_workspace_size(2, 1 << 18, TILEC) == 256 * 7 * (1 << 18) * 4
     for n in (1 << 19, 1 << 20, 1 << 21, 3 << 20):
         assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + G4, n
     n = 1 << 28
@@ -274,7 +274,13 @@ def test_pass_info(L):
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
     assert info.workspace_bytes == L.nbody_workspace_size(1, 1 << 20, TILEC)
     assert L.nbody_pass_info(2, 1 << 20, TILEC, ctypes.byref(info)) == 0
-    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 512, 2, 1024)
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
+    assert L.nbody_pass_info(2, 1 << 17, TILEC, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 2, 512)
+    assert L.nbody_pass_info(1, 1 << 16, TILEC, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 2, 512)
+    assert L.nbody_pass_info(1, 1 << 17, TILEC, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
     assert L.nbody_pass_info(1, 1 << 20, 2, ctypes.byref(info)) == 0  # FP32 running sums
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
     # FP64: FP64 partials, so the blocks grow to 2048 at 2^20 (every partial
