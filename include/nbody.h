@@ -98,9 +98,10 @@ typedef enum nb_status {
  *                 j-tile and the tile sums are added in FP64. In the
  *                 symmetric passes the tiles are the source blocks (up to
  *                 4096 particles): a particle's partial from one block is an
- *                 FP32 sum (the force pass folds its sink side into FP64
- *                 every 64 sources, as the adjoint does with two sinks per
- *                 lane), and a particle's partials are added in FP64.
+ *                 FP32 sum (the passes with up to four sinks per lane for
+ *                 the force, two for the adjoint, fold the sink side into
+ *                 FP64 every 64 sources), and a particle's partials are
+ *                 added in FP64.
  */
 typedef enum nb_prec {
     NB_F64 = 0,
@@ -145,10 +146,12 @@ typedef enum nb_op {
  *     block       threads per workgroup, waves x 64; with i_per_lane sinks
  *                 per lane, blocks of block x i_per_lane particles. Shapes
  *                 (block, i_per_lane): force (128, 2), (256, 2), (512, 2),
- *                 (1024, 2), (128, 4), (256, 4), (512, 4), (1024, 4);
+ *                 (1024, 2), (128, 4), (256, 4), (512, 4), (1024, 4), (128, 8),
+ *                 (256, 8), (512, 8);
  *                 adjoint (128, 2), (256, 2), (512, 2), (1024, 2), (256, 1),
- *                 (512, 1), (128, 4), (256, 4), (512, 4) (with four sinks per
- *                 lane each sink's sum is an FP32 running sum over the source
+ *                 (512, 1), (128, 4), (256, 4), (512, 4) (with eight sinks per
+ *                 lane for the force, and four for the adjoint, each sink's
+ *                 sum in NB_MIX_TILEC is an FP32 running sum over the source
  *                 block, as the source side's always is)
  *     split       must be 0 or 1
  * Other shapes: NB_EUNSUPPORTED. */

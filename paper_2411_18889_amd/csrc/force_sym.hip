@@ -221,7 +221,11 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
         sink_block_origin<W>(cx, cy, cz, min(a.n - I * BI, BI), org, ox, oy, oz);
     }
     C xi[K], yi[K], zi[K], mi[K];
-    typename Pol::sum_t s[K][4];
+    // the sink side: the policy's sum; with eight sinks per lane (registers
+    // are short) an FP32 running sum over the block, as the source side is
+    using Sum = typename std::conditional<(K > 4 && std::is_same<typename Pol::sum_t, SumTile>::value),
+                                          SumPlain<float>, typename Pol::sum_t>::type;
+    Sum s[K][4];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = ibase + k * 64;
@@ -251,10 +255,10 @@ __global__ __launch_bounds__(W * 64) void force_sym_kernel(SymArgs<Pol> a) {
         }
         __syncthreads();
         if (jside)
-            sym_tile<K, true, P, typename Pol::sum_t, C>(rec, &jacc[w][0][0], xi, yi, zi, mi, s,
+            sym_tile<K, true, P, Sum, C>(rec, &jacc[w][0][0], xi, yi, zi, mi, s,
                                                          a.eps2, lane);
         else
-            sym_tile<K, false, P, typename Pol::sum_t, C>(rec, nullptr, xi, yi, zi, mi, s,
+            sym_tile<K, false, P, Sum, C>(rec, nullptr, xi, yi, zi, mi, s,
                                                           a.eps2, lane);
         __syncthreads();
         if (jside) {
@@ -433,6 +437,7 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
     if (sh.waves == WV && sh.ipl == KV) e = launch_sym<Pol, WV, KV>(a, pot != nullptr, stream);
         NB_SYM_CASE(2, 2) NB_SYM_CASE(4, 2) NB_SYM_CASE(8, 2) NB_SYM_CASE(16, 2)
         NB_SYM_CASE(2, 4) NB_SYM_CASE(4, 4) NB_SYM_CASE(8, 4) NB_SYM_CASE(16, 4)
+        NB_SYM_CASE(2, 8) NB_SYM_CASE(4, 8) NB_SYM_CASE(8, 8)
 #undef NB_SYM_CASE
         if (e != hipSuccess) return e;
         f.first = I0 == 0;
@@ -455,7 +460,9 @@ constexpr size_t kSymGrowBytes = size_t(16) << 30;
 
 bool sym_shape_supported(int prec, const SymShape& s) {
     if (prec != NB_MIX_TILEC && prec != NB_F32 && prec != NB_F64) return false;
-    return (s.ipl == 2 || s.ipl == 4) && (s.waves == 2 || s.waves == 4 || s.waves == 8 || s.waves == 16);
+    return ((s.ipl == 2 || s.ipl == 4) &&
+            (s.waves == 2 || s.waves == 4 || s.waves == 8 || s.waves == 16)) ||
+           (s.ipl == 8 && (s.waves == 2 || s.waves == 4 || s.waves == 8));
 }
 
 SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
@@ -466,31 +473,45 @@ SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
 }
 
 SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
-    // Measured on MI355X with the tuner (tune.py) from 16384 to 2^20: four-
-    // wave workgroups with four sinks per lane (blocks of 1024) are fastest
-    // from 2^17 particles -- more waves per SIMD than the larger workgroups,
-    // and one source rotation per four pairs; below, blocks of 512 (65536:
-    // 0.864 ms against 0.889 with 1024) and 256. Blocks are kept to at most
-    // n/48 (>= 1176 equal work items for the 256 CUs),
-    // and grown (up to 4096) only while every FP32 partial of the pass at
-    // once (nb * 3 * n floats, or nb * 4 * n with the potential) would pass
-    // 16 GiB. The pass runs in bands when the workspace is smaller than that
-    // (SymLayout), so it serves every n up to 2^28.
+    // Measured on MI355X with the tuner (tune.py), from 16384 to 2^20:
+    //  * below 2^17 particles two sinks per lane in blocks of at most n/48
+    //    (>= 1176 equal work items for the 256 CUs): 256, or 512 from 24576
+    //    (65536: 0.864 ms against 0.889 with blocks of 1024);
+    //  * from 2^17 four-wave workgroups with four sinks per lane, blocks of
+    //    1024 (131072: 3.20 ms, the fastest symmetric shape);
+    //  * from 2^18 (FP32 and tile-compensated policies) four waves with eight
+    //    sinks per lane, blocks of 2048: one LDS record read and three
+    //    source-side rotations per eight pairs, and with FP32 block sums on
+    //    the sink side 120 VGPRs (4 waves per SIMD) against 167 (3) for four
+    //    sinks per lane -- 2^20: 199.9 ms against 207.7, 2^18: 12.93 against
+    //    12.99. The FP64 policy keeps four sinks per lane (eight take ~210
+    //    VGPRs).
+    // Blocks grow, with more waves, while every partial of the pass at once
+    // (nb * 3 * n values, or nb * 4 * n with the potential) would pass 16
+    // GiB; the pass runs in bands when the workspace is smaller (SymLayout),
+    // so it serves every n up to 2^28.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
     if ((prec != NB_MIX_TILEC && prec != NB_F32 && prec != NB_F64) || n < 48 * 256 ||
         n > (int64_t(1) << 28))
         return SymShape{0, 0};
-    static const SymShape cands[] = {{2, 2}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};  // 256 .. 4096
-    constexpr int NC = 5;
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
-    int k = 0;
-    while (k + 1 < NC && bi(cands[k + 1]) <= 1024 && bi(cands[k + 1]) <= n / 48 &&
-           (bi(cands[k + 1]) < 1024 || n >= (int64_t(1) << 17)))
-        ++k;
-    while (k + 1 < NC && sym_full_bytes(sym_layout(prec, cands[k], n, pot)) > kSymGrowBytes) ++k;
-    return cands[k];
+    auto grow = [&](const SymShape* c, int nc) {
+        int k = 0;
+        while (k + 1 < nc && sym_full_bytes(sym_layout(prec, c[k], n, pot)) > kSymGrowBytes) ++k;
+        return c[k];
+    };
+    if (n < (int64_t(1) << 17)) {
+        static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
+        return bi(small[1]) <= n / 48 ? small[1] : small[0];
+    }
+    if (n < (int64_t(1) << 18) || prec == NB_F64) {
+        static const SymShape mid[] = {{4, 4}, {8, 4}, {16, 4}};  // 1024, 2048, 4096
+        return grow(mid, 3);
+    }
+    static const SymShape large[] = {{4, 8}, {8, 8}};  // 2048, 4096
+    return grow(large, 2);
 }
 
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,

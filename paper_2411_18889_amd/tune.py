@@ -33,7 +33,8 @@ import os
 import sys
 
 # shapes the library is built for (nb_launch in include/nbody.h)
-SYM_FORCE = [(2, 128), (2, 256), (2, 512), (2, 1024), (4, 128), (4, 256), (4, 512), (4, 1024)]
+SYM_FORCE = [(2, 128), (2, 256), (2, 512), (2, 1024), (4, 128), (4, 256), (4, 512), (4, 1024),
+             (8, 128), (8, 256), (8, 512)]
 SYM_ADJOINT = [(2, 128), (2, 256), (2, 512), (2, 1024), (1, 256), (1, 512), (4, 128), (4, 256),
                (4, 512)]
 
@@ -89,10 +90,14 @@ def candidate_shapes(op, n, prec, sym_pass):
     return shapes
 
 
-def tune(n, prec, op="force", eps=2.0 ** -8, shapes=None, reps=None, seed=5, one_sided=True):
+def tune(n, prec, op="force", eps=2.0 ** -8, shapes=None, reps=None, seed=5, one_sided=True,
+         adjoint_pass="walk"):
     """Times every shape (or `shapes`, a list of nb_launch dicts or of
     (i_per_lane, block, split) one-sided triples) of the `op` pass at n.
-    one_sided=False leaves the one-sided family out of the default sweep."""
+    one_sided=False leaves the one-sided family out of the default sweep.
+    adjoint_pass: "walk" (a walked-back step, the pass with the force sums)
+    or "entry" (the entry pass, without them, as every pass of a walk over
+    a state checkpointed at every step)."""
     import numpy as np
     import torch
 
@@ -133,9 +138,13 @@ def tune(n, prec, op="force", eps=2.0 ** -8, shapes=None, reps=None, seed=5, one
             st["lx"], st["lv"] = torch.zeros_like(lam), lam.clone()
             st["lm"] = torch.zeros(n, dtype=torch.float64, device=dev)
 
-        def run(launch):  # one walked-back step: reverse drift + a pass with the force sums
-            api.step_adjoint(st["x"], st["v"], M, st["a"], st["lx"], st["lv"], st["lm"], eps,
-                             2.0 ** -16, 1, prec=prec, launch=launch)
+        def run(launch):
+            if adjoint_pass == "walk":  # one walked-back step: reverse drift + a pass with the force sums
+                api.step_adjoint(st["x"], st["v"], M, st["a"], st["lx"], st["lv"], st["lm"], eps,
+                                 2.0 ** -16, 1, prec=prec, launch=launch)
+            else:  # the entry pass: J^T lam and G^T lam at x, no force sums
+                api.step_adjoint(st["x"], st["v"], M, st["a"], st["lx"], st["lv"], st["lm"], eps,
+                                 2.0 ** -16, 0, prec=prec, launch=launch, entry_half=True)
 
         def compare(launch):
             reset()
@@ -164,7 +173,8 @@ def tune(n, prec, op="force", eps=2.0 ** -8, shapes=None, reps=None, seed=5, one
     t_lib = min(t_lib, _time(lib_call, reps, reset))
     rows.sort(key=lambda r: r[0])
     info = api.pass_info(1 if op == "force" else 2, n, prec)
-    return {"op": op, "n": n, "prec": prec, "best": best[1], "best_ms": best[0],
+    return {"op": op if op == "force" else "adjoint-" + adjoint_pass, "n": n, "prec": prec,
+            "best": best[1], "best_ms": best[0],
             "best_gpairs_per_s": n * n / best[0] / 1e6, "library_ms": t_lib,
             "library_shape": {k: info[k] for k in ("symmetric", "block", "i_per_lane", "split")},
             "library_gpairs_per_s": n * n / t_lib / 1e6,
@@ -179,12 +189,15 @@ def main(argv=None):
     ap.add_argument("--op", nargs="+", default=["force"], choices=["force", "adjoint"])
     ap.add_argument("--symmetric-only", action="store_true",
                     help="sweep the symmetric pass's shapes only")
+    ap.add_argument("--adjoint-pass", default="walk", choices=["walk", "entry"],
+                    help="the adjoint pass timed: a walked-back step (with the force sums) or "
+                         "the entry pass (without them)")
     args = ap.parse_args(argv)
     for op in args.op:
         for prec in args.prec:
             for n in args.n:
-                print(json.dumps(tune(n, prec, op=op, one_sided=not args.symmetric_only)),
-                      flush=True)
+                print(json.dumps(tune(n, prec, op=op, one_sided=not args.symmetric_only,
+                                      adjoint_pass=args.adjoint_pass)), flush=True)
 
 
 if __name__ == "__main__":

@@ -33,7 +33,7 @@ int main(void)
           "symmetric step workspace at 2^20");
     memset(&info, 0, sizeof(info));
     check(nbody_pass_info(NB_OP_STEP, 1 << 20, NB_MIX_TILEC, &info) == NB_OK, "pass_info");
-    check(info.symmetric == 1 && info.block_particles == 1024, "symmetric pass at 2^20");
+    check(info.symmetric == 1 && info.block_particles == 2048, "symmetric pass at 2^20");
     check(nbody_pass_info(NB_OP_STEP, 1000, NB_MIX_TILEC, &info) == NB_OK && info.symmetric == 0,
           "one-sided pass at 1000");
     check(nbody_pass_info(NB_OP_STEP, 0, NB_F64, &info) == NB_EINVAL, "pass_info n = 0");

@@ -67,13 +67,15 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
     # a set acting on itself with the tile-compensated policy from 12288 on:
     # the symmetric pass, one FP32 partial per particle, component and block
-    # (blocks of at most min(n/48, 1024) particles, larger while every partial
-    # at once would pass 16 GiB); the whole set of partials up to 4 GiB
+    # (blocks of at most min(n/48, 512) particles below 2^17, 1024 up to 2^18,
+    # 2048 from there, larger while every partial at once would pass 16 GiB);
+    # the whole set of partials up to 4 GiB
     assert L.nbody_workspace_size(1, 12288, TILEC) == 48 * 3 * 12288 * 4
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
     assert L.nbody_workspace_size(1, 24576, TILEC) == 48 * 3 * 24576 * 4
     assert L.nbody_workspace_size(1, 32768, TILEC) == 64 * 3 * 32768 * 4
-    assert L.nbody_workspace_size(1, 1 << 18, TILEC) == 256 * 3 * (1 << 18) * 4
+    assert L.nbody_workspace_size(1, 1 << 17, TILEC) == 128 * 3 * (1 << 17) * 4
+    assert L.nbody_workspace_size(1, 1 << 18, TILEC) == 128 * 3 * (1 << 18) * 4
     # beyond 4 GiB of partials the pass runs in bands of about 4 GiB, after
     # FP64 running sums (3 per particle)
     G4 = 4 << 30
@@ -91,7 +93,7 @@ def test_workspace_size(L):
     # nbody_accel covers the symmetric pass with the potential too: four
     # partials (and running sums) per particle
     assert L.nbody_workspace_size(0, 1 << 20, TILEC) == 4 * (1 << 20) * 8 + G4
-    assert L.nbody_workspace_size(0, 1 << 18, TILEC) == 256 * 4 * (1 << 18) * 4
+    assert L.nbody_workspace_size(0, 1 << 18, TILEC) == 128 * 4 * (1 << 18) * 4
     # and a small sink set against up to n sources: at most 64 one-tile source
     # ranges below 16384 sources, n / 512 above, <= 2^24 sink-ranges in all,
     # 4 FP64 partials each
@@ -271,7 +273,7 @@ def test_pass_info(L):
     from paper_2411_18889_amd import _lib
     info = _lib.nb_pass_info()
     assert L.nbody_pass_info(1, 1 << 20, TILEC, ctypes.byref(info)) == 0
-    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 8, 2048)
     assert info.workspace_bytes == L.nbody_workspace_size(1, 1 << 20, TILEC)
     assert L.nbody_pass_info(2, 1 << 20, TILEC, ctypes.byref(info)) == 0
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
@@ -283,10 +285,14 @@ def test_pass_info(L):
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
     assert L.nbody_pass_info(1, 1 << 20, 2, ctypes.byref(info)) == 0  # FP32 running sums
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
-    # FP64: FP64 partials, so the blocks grow to 2048 at 2^20 (every partial
-    # at once would pass 16 GiB with 1024)
+    assert L.nbody_pass_info(1, 1 << 18, TILEC, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 8, 2048)
+    # FP64: four sinks per lane, FP64 partials, so the blocks grow to 2048 at
+    # 2^20 (every partial at once would pass 16 GiB with 1024)
+    assert L.nbody_pass_info(1, 1 << 18, F64, ctypes.byref(info)) == 0
+    assert (info.i_per_lane, info.block_particles) == (4, 1024)
     assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
-    assert (info.symmetric, info.block_particles) == (1, 2048)
+    assert (info.symmetric, info.i_per_lane, info.block_particles) == (1, 4, 2048)
     assert info.workspace_bytes == 3 * (1 << 20) * 8 + (4 << 30)
     # the symmetric passes now serve every size up to 2^28: blocks of 4096
     # (force) and 2048 (adjoint) at the top
