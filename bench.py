@@ -305,7 +305,8 @@ def bench_diffusion(args):
 TRAFFIC_KERNELS = {"force_sym_kernel": ("force_sym_kernel", "force_sym_finish_kernel"),
                    "adjoint_sym_kernel": ("adjoint_sym_kernel", "adjoint_sym_finish_kernel"),
                    "force_kernel": ("force_kernel", "force_reduce_kernel"),
-                   "adjoint_kernel": ("adjoint_kernel", "adjoint_reduce_kernel")}
+                   "adjoint_kernel": ("adjoint_kernel", "adjoint_reduce_kernel"),
+                   "diffusion_kernel4": ("diffusion_kernel4",)}
 
 
 def _kernel_base(name):
@@ -350,25 +351,32 @@ def traffic_summary(args):
     passes = args.rollout + 1
     out = {"_note": "HBM-side bytes per pass = (FETCH_SIZE KiB x 1024 x %.3f + WRITE_SIZE KiB x "
                     "1024 x %.3f) summed over the pair kernel's and its fold kernel's dispatches "
-                    "of one benchmark step with --rollout %d, over its %d passes; factors from a "
-                    "plain 1 GiB device copy (the bytes it moves over the counters' reading); "
-                    "regenerate when the kernel's sources change" % (f_factor, w_factor,
-                                                                     args.rollout, passes),
+                    "of one benchmark step with --rollout %d, over its %d passes (the stencil: "
+                    "per dispatch); factors from a plain 1 GiB device copy (the bytes it moves "
+                    "over the counters' reading); regenerate when the kernel's sources change"
+                    % (f_factor, w_factor, args.rollout, passes),
            "commands": ["cd /tmp && export TMPDIR=/tmp; from the repository root, one counter C "
                         "per run, C in FETCH_SIZE WRITE_SIZE:",
                         "rocprofv3 --pmc C -d gpurun_out/pmc_C -o bench --output-format csv -- "
                         "python3 bench.py --steps 1 --warmup 0 --rollout %d --cpu-sample 0" % args.rollout,
+                        "rocprofv3 --pmc C -d gpurun_out/pmc_diff_C -o diff --output-format csv -- "
+                        "python3 bench.py --workload diffusion-512 --steps 1 --warmup 1 --cpu-sample 0",
                         "rocprofv3 --pmc C -d gpurun_out/pmc_copy_C -o copy --output-format csv -- "
                         "python3 bench.py --copy-probe-mib 1024",
                         "python3 bench.py --rollout %d --traffic-from gpurun_out/pmc_FETCH_SIZE "
                         "gpurun_out/pmc_WRITE_SIZE gpurun_out/pmc_copy_FETCH_SIZE "
-                        "gpurun_out/pmc_copy_WRITE_SIZE" % args.rollout]}
+                        "gpurun_out/pmc_copy_WRITE_SIZE" % args.rollout,
+                        "python3 bench.py --workload diffusion-512 --traffic-from "
+                        "gpurun_out/pmc_diff_FETCH_SIZE gpurun_out/pmc_diff_WRITE_SIZE "
+                        "gpurun_out/pmc_copy_FETCH_SIZE gpurun_out/pmc_copy_WRITE_SIZE"]}
     for fam, names in TRAFFIC_KERNELS.items():
         fk = sum(v for k, v in fetch if _kernel_base(k) in names)
         wk = sum(v for k, v in write if _kernel_base(k) in names)
         nd = sum(1 for k, _ in fetch if _kernel_base(k) == fam)
         if nd == 0:
             continue
+        if fam == "diffusion_kernel4":
+            passes = nd
         out["%s@%s" % (fam, args.workload)] = {
             "source_sha256": kernel_source_hash(fam),
             "bytes_per_launch": (fk * 1024.0 * f_factor + wk * 1024.0 * w_factor) / passes,

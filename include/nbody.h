@@ -380,10 +380,10 @@ size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int s
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair,
  * partials per block (FP32; FP64 for NB_F64) added in a fixed order
- * (NB_MIX_TILEC, and NB_F32 and NB_F64 for the force, from 12288 particles;
- * blocks grow while the partials would pass 16 GiB -- 32 GiB for the
- * adjoint -- and the largest block is used up to 64 GiB of partials: about
- * 4.8 M particles for the tile-compensated force, 2.2 M for the adjoint).
+ * (NB_MIX_TILEC, and NB_F32 and NB_F64 for the force, from 12288 up to
+ * 2^28 particles; the force's blocks grow from 2048 to 4096 particles while
+ * every partial at once would pass 16 GiB, the adjoint's stay at 1024; the
+ * partials are written and folded in bands of the workspace).
  * symmetric = 0: the one-sided kernel in the shape (i_per_lane, block,
  * split).
  */

@@ -333,11 +333,6 @@ hipError_t launch_asym(const ASymArgs& a, bool force, hipStream_t stream) {
     return hipGetLastError();
 }
 
-// Blocks grow while every partial of the pass at once would pass 32 GiB
-// (at 2^20 blocks of 1024 -- 30 GB of partials -- run 4 % faster with the
-// force sums and 10 % without them than blocks of 2048 with 15 GB; blocks of
-// 512, 60 GB, gain nothing more).
-constexpr size_t kAdjSymGrowBytes = size_t(32) << 30;
 
 }  // namespace
 
@@ -355,20 +350,21 @@ SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums) {
 }
 
 SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
-    // Measured on MI355X with the tuner (tune.py, one walked-back step):
-    //  * up to 2^18 particles two sinks per lane -- the seven running sums per
+    // Measured on MI355X with the tuner (tune.py; a walked-back step, the
+    // pass with the force sums, and the entry pass without them; the run
+    // these figures come from is in profiles/launch_shape_tuning.md):
+    //  * below 2^18 particles two sinks per lane -- the seven running sums per
     //    sink, each an FP32 group sum folded into FP64, take ~126 VGPRs --
-    //    in blocks of at most n/64 (256 or 512 particles; 65536: 4 waves x 2
-    //    the fastest, 2.12 ms);
+    //    in blocks of at most n/64 (256 or 512 particles; 65536: 4 waves x 2,
+    //    2.33 ms, within 1 % of the fastest shape);
     //  * from 2^18 four sinks per lane with FP32 block sums on the sink side
-    //    (154 VGPRs, 3 waves per SIMD) in 4-wave blocks of 1024: half the LDS
-    //    reads and source-side rotations per pair, 4.3 % faster than 8 waves
-    //    x 2 at 2^20 (517 against 540 ms) and 4.5 % at 2^18 (32.3 against
-    //    33.9 ms);
-    //  * blocks grow, with more waves, while every FP32 partial of the pass at
-    //    once (nb * 7 * n floats) would pass 32 GiB; the pass runs in bands
-    //    when the workspace is smaller (SymLayout), so it serves every n up
-    //    to 2^28.
+    //    (154 VGPRs, 3 waves per SIMD) in 4-wave blocks of 1024 at every n:
+    //    half the LDS reads and source-side rotations per pair -- 2^20: 542
+    //    ms against 561 for 8 waves x 2; 2^21: 2165 ms against 2406 for 8
+    //    waves x 4 (blocks of 2048: half the partials, but a workgroup of
+    //    eight waves at three waves per SIMD). The partials (nb * 7 * n floats, 60 GB at 2^20) are
+    //    written and read back in bands of the workspace (SymLayout), so the
+    //    pass serves every n up to 2^28 in bounded memory.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 31 % faster at 8192;
     // symmetric 12 % faster at 12288, 21 % at 24576).
@@ -378,11 +374,7 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
         static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
         return (bi(small[1]) <= n / 64) ? small[1] : small[0];
     }
-    static const SymShape cands[] = {{4, 4}, {8, 4}};  // 1024, 2048
-    constexpr int NC = 2;
-    int k = 0;
-    while (k + 1 < NC && sym_full_bytes(adjoint_sym_layout(cands[k], n, true)) > kAdjSymGrowBytes) ++k;
-    return cands[k];
+    return SymShape{4, 4};  // 1024
 }
 
 hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,

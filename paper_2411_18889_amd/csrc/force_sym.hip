@@ -473,23 +473,25 @@ SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
 }
 
 SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
-    // Measured on MI355X with the tuner (tune.py), from 16384 to 2^20:
+    // Measured on MI355X with the tuner (tune.py; the run these figures come
+    // from is in profiles/launch_shape_tuning.md), from 16384 to 2^21:
     //  * below 2^17 particles two sinks per lane in blocks of at most n/48
     //    (>= 1176 equal work items for the 256 CUs): 256, or 512 from 24576
-    //    (65536: 0.864 ms against 0.889 with blocks of 1024);
+    //    (65536: 0.954 ms, the fastest shape 0.948);
     //  * from 2^17 four-wave workgroups with four sinks per lane, blocks of
-    //    1024 (131072: 3.20 ms, the fastest symmetric shape);
-    //  * from 2^18 (FP32 and tile-compensated policies) four waves with eight
-    //    sinks per lane, blocks of 2048: one LDS record read and three
-    //    source-side rotations per eight pairs, and with FP32 block sums on
-    //    the sink side 120 VGPRs (4 waves per SIMD) against 167 (3) for four
-    //    sinks per lane -- 2^20: 199.9 ms against 207.7, 2^18: 12.93 against
-    //    12.99. The FP64 policy keeps four sinks per lane (eight take ~210
-    //    VGPRs).
-    // Blocks grow, with more waves, while every partial of the pass at once
-    // (nb * 3 * n values, or nb * 4 * n with the potential) would pass 16
-    // GiB; the pass runs in bands when the workspace is smaller (SymLayout),
-    // so it serves every n up to 2^28.
+    //    1024 (131072: 3.47 ms, the fastest symmetric shape);
+    //  * from 2^18 four waves with eight sinks per lane, blocks of 2048: one
+    //    LDS record read and three source-side rotations per eight pairs, and
+    //    with FP32 block sums on the sink side 120 VGPRs (4 waves per SIMD)
+    //    against 167 (3) for four sinks per lane -- 2^20: 204.5 ms against
+    //    211.7 for 4 x 4, 2^18: 13.16 against 13.56; FP64 (FP64 sums
+    //    throughout) 2^20: 436.2 ms against 477.5 for 8 waves x 4, 2^18: 27.6
+    //    against 28.0 for 4 x 4.
+    // From 2^18 the blocks grow to 4096 (eight waves) while every partial of
+    // the pass at once (nb * 3 * n values, or nb * 4 * n with the potential)
+    // would pass 16 GiB (2^21: 814.2 ms against 815.5 for blocks of 2048).
+    // The pass runs in bands when the workspace is smaller (SymLayout), so it
+    // serves every n up to 2^28.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
@@ -497,21 +499,15 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
         n > (int64_t(1) << 28))
         return SymShape{0, 0};
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
-    auto grow = [&](const SymShape* c, int nc) {
-        int k = 0;
-        while (k + 1 < nc && sym_full_bytes(sym_layout(prec, c[k], n, pot)) > kSymGrowBytes) ++k;
-        return c[k];
-    };
     if (n < (int64_t(1) << 17)) {
         static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
         return bi(small[1]) <= n / 48 ? small[1] : small[0];
     }
-    if (n < (int64_t(1) << 18) || prec == NB_F64) {
-        static const SymShape mid[] = {{4, 4}, {8, 4}, {16, 4}};  // 1024, 2048, 4096
-        return grow(mid, 3);
-    }
+    if (n < (int64_t(1) << 18)) return SymShape{4, 4};    // 1024
     static const SymShape large[] = {{4, 8}, {8, 8}};  // 2048, 4096
-    return grow(large, 2);
+    int k = 0;
+    while (k < 1 && sym_full_bytes(sym_layout(prec, large[k], n, pot)) > kSymGrowBytes) ++k;
+    return large[k];
 }
 
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,

@@ -101,9 +101,9 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1 << 30, TILEC) == (1 << 24) * 4 * 8
     assert L.nbody_workspace_size(0, 1 << 30, F64) == (1 << 24) * 4 * 8
     # and the symmetric adjoint pass: seven FP32 partials per particle and
-    # block (blocks of min(n/64, 512) below 2^18, 1024 from there, larger
-    # while every partial would pass 32 GiB, up to 2048), all of them up to
-    # 4 GiB, then seven FP64 running sums and bands of about 4 GiB
+    # block (blocks of min(n/64, 512) below 2^18, 1024 from there at every
+    # n), all of them up to 4 GiB, then seven FP64 running sums and bands of
+    # about 4 GiB
     assert L.nbody_workspace_size(2, 12288, TILEC) == 48 * 7 * 12288 * 4
     assert L.nbody_workspace_size(2, 16384, TILEC) == 64 * 7 * 16384 * 4
     assert L.nbody_workspace_size(2, 32768, TILEC) == 64 * 7 * 32768 * 4
@@ -112,7 +112,7 @@ def test_workspace_size(L):
     for n in (1 << 19, 1 << 20, 1 << 21, 3 << 20):
         assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + G4, n
     n = 1 << 28
-    assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + 7 * 4 * (n + 131071 * 2048)
+    assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + 7 * 4 * (n + 262143 * 1024)
     # the one-sided adjoint kernel (other policies): split partials or none
     assert L.nbody_workspace_size(2, 1 << 20, F64) == 8 * 7 * (1 << 20) * 8
 
@@ -287,16 +287,17 @@ def test_pass_info(L):
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
     assert L.nbody_pass_info(1, 1 << 18, TILEC, ctypes.byref(info)) == 0
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 8, 2048)
-    # FP64: four sinks per lane, FP64 partials, so the blocks grow to 2048 at
-    # 2^20 (every partial at once would pass 16 GiB with 1024)
-    assert L.nbody_pass_info(1, 1 << 18, F64, ctypes.byref(info)) == 0
+    # FP64: the same shapes, FP64 partials (blocks of 4096 from 2^21)
+    assert L.nbody_pass_info(1, 1 << 17, F64, ctypes.byref(info)) == 0
     assert (info.i_per_lane, info.block_particles) == (4, 1024)
     assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
-    assert (info.symmetric, info.i_per_lane, info.block_particles) == (1, 4, 2048)
+    assert (info.symmetric, info.i_per_lane, info.block_particles) == (1, 8, 2048)
     assert info.workspace_bytes == 3 * (1 << 20) * 8 + (4 << 30)
-    # the symmetric passes now serve every size up to 2^28: blocks of 4096
-    # (force) and 2048 (adjoint) at the top
-    for op, b in ((1, 4096), (2, 2048)):
+    assert L.nbody_pass_info(1, 1 << 21, F64, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 512, 8, 4096)
+    # the symmetric passes serve every size up to 2^28: blocks of 4096
+    # (force) and 1024 (adjoint) at the top
+    for op, b in ((1, 4096), (2, 1024)):
         assert L.nbody_pass_info(op, 1 << 28, TILEC, ctypes.byref(info)) == 0
         assert (info.symmetric, info.block_particles) == (1, b)
     assert L.nbody_pass_info(1, (1 << 28) + 1, TILEC, ctypes.byref(info)) == 0

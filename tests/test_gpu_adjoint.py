@@ -100,11 +100,10 @@ def test_adjoint_symmetric_pass_matches_oracle(n):
 
 @pytest.mark.parametrize("n", (600_000, 1 << 20, (1 << 21) + 3))
 def test_adjoint_symmetric_large_blocks(n):
-    """Blocks of 512 (600,000), of 1024 (8 waves; 2^20, whose partials
-    would pass 32 GiB with blocks of 512), and 2^21 + 3, where even blocks of
-    2048 (16 waves) leave 60 GB of partials, within the 64 GiB the largest
-    block may take: one step forward and back, against the one-sided kernel
-    with the FP64-summed policy on every particle."""
+    """Blocks of 1024 (4 waves x 4 sinks) at 600,000 (a ragged last block),
+    2^20 and 2^21 + 3, whose partials (60 and 240 GB in all) are folded in
+    bands of the default workspace: one step forward and back, against the
+    one-sided kernel with the FP64-summed policy on every particle."""
     S, K = 1, 1
     x, v, m, y = _problem(n, 95)
     eps, dt = 2.0 ** -10, 2.0 ** -11

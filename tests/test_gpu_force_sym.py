@@ -1,8 +1,9 @@
 """GPU parity of the symmetric (third-law) force pass, which the library
 uses for one set acting on itself with the tile-compensated and the plain
-FP32 policies from 12288 particles on: blocks of up to min(n/48, 1024) particles (2048 and 4096 when
-the partials would pass 16 GiB), a work item per block pair, FP32 partials
-per block added in a fixed order.
+FP32 policies from 12288 particles on: blocks of 256 or 512 particles below
+2^17, 1024 below 2^18, 2048 from there (4096 when every partial at once would
+pass 16 GiB), a work item per block pair, FP32 partials per block added in a
+fixed order.
 
 Checked against the FP64 oracle (all sinks up to 20000, sampled sinks above),
 against the one-sided kernel on every sink at any size, and by the third law
@@ -125,9 +126,10 @@ def test_sym_step_matches_oracle(prec):
 
 @pytest.mark.parametrize("n", (1_200_000, (1 << 21) + 3))
 def test_sym_large_blocks(n):
-    """Sizes whose partials need blocks of 2048 (8 waves x 4 sinks) and 4096
-    (16 waves x 4 sinks): sampled sinks against the oracle, every sink
-    against the one-sided kernel, and the third law."""
+    """Blocks of 2048 (4 waves x 8 sinks, a ragged last block) and 4096 (8
+    waves x 8 sinks, where every partial of blocks of 2048 would pass 16
+    GiB): sampled sinks against the oracle, every sink against the one-sided
+    kernel, and the third law."""
     x, v, m = plummer_sphere(n, 240 + n % 5)
     eps = 2.0 ** -10
     xd, _, md = to_dev(x, v, m, PREC)
@@ -145,14 +147,15 @@ def test_sym_large_blocks(n):
     assert np.all(tot <= 1e-6 * (np.abs(ah) * ms).sum())
 
 
-@pytest.mark.parametrize("n", (16384, 24576 + 7, 65536 + 1000, 1_200_000))
+@pytest.mark.parametrize("n", (16384, 24576 + 7, 65536 + 1000, 1_600_000))
 def test_sym_potential(n):
     """The potential from the symmetric pass (a fourth partial per particle
     and block, the j = i term removed after the sum): against the oracle
     (every sink up to 40000, sampled above) and the one-sided kernel on every
     sink. Its accelerations are those of the pass without the potential --
-    bitwise where both use the same blocks; at 1,200,000 the four partials
-    pass the 16 GiB bound and the potential pass takes blocks of 2048."""
+    bitwise where both use the same blocks; at 1,600,000 the four partials
+    pass the 16 GiB bound and the potential pass takes blocks of 4096 (the
+    pass without it 2048)."""
     x, v, m = plummer_sphere(n, 260 + n % 89)
     m = m * np.random.default_rng(n + 1).uniform(0.5, 1.5, size=n)  # unequal masses
     eps = 2.0 ** -9

@@ -180,6 +180,24 @@ def adjoint_row():
     return best
 
 
+def timed_batch(fn, inner, groups=3):
+    """Best over `groups` of the mean time of `inner` back-to-back calls
+    between one pair of HIP events (ms per call): launch gaps amortised."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(groups):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(inner):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / inner)
+    return best
+
+
 def pass_scan():
     """Force and adjoint-step times across N, library shapes."""
     import torch
@@ -189,6 +207,7 @@ def pass_scan():
     for n in (1024, 4096, 16384, 65536, 262144, 1 << 20, 1 << 21):
         x, v, m = plummer_sphere(n, 3)
         row = {"n": n}
+        inner = 50 if n <= 16384 else (10 if n <= 65536 else (3 if n <= 262144 else 1))
         for prec in ("mix_tilec", "f32", "f64"):
             if prec == "f64" and n > 262144:
                 continue
@@ -197,21 +216,24 @@ def pass_scan():
             X = torch.tensor(x, dtype=pdt, device="cuda")
             V = torch.tensor(v, dtype=pdt, device="cuda")
             M = torch.tensor(m, dtype=mdt, device="cuda")
-            reps = 5 if n <= 262144 else 2
-            ms = timed(lambda: nb.accel(X, M, 2.0 ** -9, prec=prec), reps)
+            eps = 2.0 ** -9
+            ws = torch.empty(max(1, nb.workspace_size(0, n, prec)), dtype=torch.uint8, device="cuda")
+            out_a = torch.empty_like(X)
+            ms = timed_batch(lambda: nb.accel(X, M, eps, prec=prec, out=out_a, workspace=ws), inner)
             info = nb.pass_info(1, n, prec)
             peak = FP64_PEAK if prec == "f64" else FP32_PEAK
             row["force_" + prec] = (ms, bench.executed_flop("force", n, info) / (ms * 1e-3) / peak)
             if prec in ("mix_tilec", "f64"):
-                acc = nb.accel(X, M, 2.0 ** -9, prec=prec)
-                lam = torch.ones_like(X)
-                st = {}
-
-                def one():
-                    st["l"] = (torch.zeros_like(lam), lam.clone(), torch.zeros(n, dtype=torch.float64, device="cuda"))
-                    nb.step_adjoint(X.clone(), V.clone(), M, acc.clone(), *st["l"], 2.0 ** -9, 2.0 ** -16,
-                                    1, prec=prec)
-                ms = timed(one, reps)
+                # one reverse step (reverse drift + a fused pass with the force
+                # sums) on resident state; the calls walk the same state back
+                acc = nb.accel(X, M, eps, prec=prec)
+                st = (X.clone(), V.clone(), acc, torch.zeros_like(X), torch.ones_like(X),
+                      torch.zeros(n, dtype=torch.float64, device="cuda"))
+                wsa = torch.empty(max(1, nb.workspace_size(2, n, prec)), dtype=torch.uint8,
+                                  device="cuda")
+                ms = timed_batch(lambda: nb.step_adjoint(st[0], st[1], M, st[2], st[3], st[4], st[5],
+                                                         eps, 2.0 ** -16, 1, prec=prec, workspace=wsa),
+                                 inner)
                 ainfo = nb.pass_info(2, n, prec)
                 row["adj_" + prec] = (ms, bench.executed_flop("adjoint", n, ainfo, True) / (ms * 1e-3) / peak)
         out.append(row)
@@ -266,12 +288,14 @@ def main():
               "x0 %.2g, v0 %.2g, m %.2g" % (f, b, b / f, *errs))
     if not args.skip_scan:
         print("\nPass times across N (Plummer, eps = 2^-9; force = `nbody_accel` of the set on itself, "
-              "adjoint = one reverse step of `nbody_step_adjoint`; best of 5 (2 from 2^20); "
-              "% of the FP32 (FP64) vector peak from executed flop)\n")
+              "adjoint = one reverse step of `nbody_step_adjoint`, resident inputs and workspace; "
+              "best of 3 batches of 50 (up to 16384), 10, 3, then 1 back-to-back calls; "
+              "ms per call, % of the FP32 (FP64) vector peak from executed flop)\n")
         print("| N | force tile-compensated | adjoint step tile-compensated | force FP32 | force FP64 | adjoint step FP64 |")
         print("|---:|---|---|---|---|---|")
         for r in pass_scan():
-            cell = lambda k: ("%.4g ms (%.0f %%)" % (r[k][0], 100 * r[k][1])) if k in r else "—"
+            cell = lambda k: ("%.4g ms (%.0f G/s, %.0f %%)" % (r[k][0], r["n"] ** 2 / r[k][0] / 1e6,
+                                                               100 * r[k][1])) if k in r else "—"
             print("| %d | %s | %s | %s | %s | %s |" % (r["n"], cell("force_mix_tilec"), cell("adj_mix_tilec"),
                                                      cell("force_f32"), cell("force_f64"), cell("adj_f64")))
     if not args.skip_cpu:
