@@ -361,8 +361,9 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     //    (154 VGPRs, 3 waves per SIMD) in 4-wave blocks of 1024 at every n:
     //    half the LDS reads and source-side rotations per pair -- 2^20: 542
     //    ms against 561 for 8 waves x 2; 2^21: 2165 ms against 2406 for 8
-    //    waves x 4 (blocks of 2048: half the partials, but a workgroup of
-    //    eight waves at three waves per SIMD). The partials (nb * 7 * n floats, 60 GB at 2^20) are
+    //    waves x 4 (blocks of 2048: half the partials, but with 154 VGPRs a
+    //    CU holds one eight-wave workgroup, two waves per SIMD, against three
+    //    four-wave ones). The partials (nb * 7 * n floats, 60 GB at 2^20) are
     //    written and read back in bands of the workspace (SymLayout), so the
     //    pass serves every n up to 2^28 in bounded memory.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
