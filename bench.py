@@ -351,10 +351,11 @@ def traffic_summary(args):
     passes = args.rollout + 1
     out = {"_note": "HBM-side bytes per pass = (FETCH_SIZE KiB x 1024 x %.3f + WRITE_SIZE KiB x "
                     "1024 x %.3f) summed over the pair kernel's and its fold kernel's dispatches "
-                    "of one benchmark step with --rollout %d, over its %d passes (the stencil: "
-                    "per dispatch); factors from a plain 1 GiB device copy (the bytes it moves "
-                    "over the counters' reading); regenerate when the kernel's sources change"
-                    % (f_factor, w_factor, args.rollout, passes),
+                    "of the profiled benchmark step, over the passes of that step (each entry's "
+                    "'passes': R + 1 for a step with --rollout R; the stencil: per dispatch); "
+                    "factors from a plain 1 GiB device copy (the bytes it moves over the "
+                    "counters' reading); regenerate when the kernel's sources change"
+                    % (f_factor, w_factor),
            "commands": ["cd /tmp && export TMPDIR=/tmp; from the repository root, one counter C "
                         "per run, C in FETCH_SIZE WRITE_SIZE:",
                         "rocprofv3 --pmc C -d gpurun_out/pmc_C -o bench --output-format csv -- "
@@ -563,8 +564,14 @@ def main():
         b = int(info["block_particles"])
         return float((n + b - 1) // b) * nq * n * 4
 
-    roof_adj = roofline(ak, apass, a_flop, a_ms, FLOP_PER_INTERACTION_ADJOINT, a_off, a_one,
-                        " (fused force + J^T lam + G^T lam)",
+    # the paper-style count of the adjoint: 55 flop per interaction for a
+    # pass that also sums the force, 48 (the one-sided count without the
+    # force sums) for one that reloads it, averaged over the walk
+    conv_adj = (nF * FLOP_PER_INTERACTION_ADJOINT
+                + nNoF * EXEC_FLOP[("adjoint", False, False)]) / (nF + nNoF)
+    roof_adj = roofline(ak, apass, a_flop, a_ms, conv_adj, a_off, a_one,
+                        " (fused J^T lam + G^T lam; the force sums in %d of %d passes)"
+                        % (nF, nF + nNoF),
                         (nF * partials(apass, 7) + nNoF * partials(apass, 4)) / (nF + nNoF))
     roof_adj["passes_with_force_sums"], roof_adj["passes_without"] = nF, nNoF
     force_roof = roofline(fk, fpass, f_flop, f_ms, FLOP_PER_INTERACTION_FORCE, f_off, f_one, "",

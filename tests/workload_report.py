@@ -209,7 +209,7 @@ def pass_scan():
         row = {"n": n}
         inner = 50 if n <= 16384 else (10 if n <= 65536 else (3 if n <= 262144 else 1))
         for prec in ("mix_tilec", "f32", "f64"):
-            if prec == "f64" and n > 262144:
+            if prec == "f64" and n > (1 << 20):
                 continue
             log("scan n=%d %s" % (n, prec))
             pdt, mdt = nb.pos_dtype(prec), nb.mass_dtype(prec)
@@ -223,6 +223,10 @@ def pass_scan():
             info = nb.pass_info(1, n, prec)
             peak = FP64_PEAK if prec == "f64" else FP32_PEAK
             row["force_" + prec] = (ms, bench.executed_flop("force", n, info) / (ms * 1e-3) / peak)
+            if prec == "mix_tilec":
+                ms = timed_batch(lambda: nb.accel(X, M, eps, prec=prec, potential=True, out=out_a,
+                                                  workspace=ws), inner)
+                row["pot"] = (ms, None)
             if prec in ("mix_tilec", "f64"):
                 # one reverse step (reverse drift + a fused pass with the force
                 # sums) on resident state; the calls walk the same state back
@@ -291,13 +295,19 @@ def main():
               "adjoint = one reverse step of `nbody_step_adjoint`, resident inputs and workspace; "
               "best of 3 batches of 50 (up to 16384), 10, 3, then 1 back-to-back calls; "
               "ms per call, % of the FP32 (FP64) vector peak from executed flop)\n")
-        print("| N | force tile-compensated | adjoint step tile-compensated | force FP32 | force FP64 | adjoint step FP64 |")
-        print("|---:|---|---|---|---|---|")
+        print("| N | force tile-compensated | force + potential tile-compensated | adjoint step tile-compensated "
+              "| force FP32 | force FP64 | adjoint step FP64 |")
+        print("|---:|---|---|---|---|---|---|")
         for r in pass_scan():
-            cell = lambda k: ("%.4g ms (%.0f G/s, %.0f %%)" % (r[k][0], r["n"] ** 2 / r[k][0] / 1e6,
-                                                               100 * r[k][1])) if k in r else "—"
-            print("| %d | %s | %s | %s | %s | %s |" % (r["n"], cell("force_mix_tilec"), cell("adj_mix_tilec"),
-                                                     cell("force_f32"), cell("force_f64"), cell("adj_f64")))
+            def cell(k):
+                if k not in r:
+                    return "—"
+                ms, frac = r[k]
+                g = "%.4g ms (%.0f G/s" % (ms, r["n"] ** 2 / ms / 1e6)
+                return g + (", %.0f %%)" % (100 * frac) if frac is not None else ")")
+            print("| %d | %s | %s | %s | %s | %s | %s |" % (
+                r["n"], cell("force_mix_tilec"), cell("pot"), cell("adj_mix_tilec"), cell("force_f32"),
+                cell("force_f64"), cell("adj_f64")))
     if not args.skip_cpu:
         rows, k0 = cpu_table()
         print("\nFP64 oracle (`oracle_accel`) on the host: Ginteractions/s (sampled sinks x all N)\n")
