@@ -371,8 +371,7 @@ size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int s
  * nbody_pass_info -- the pair pass the library runs for n particles acting
  * on themselves (op NB_OP_STEP: the force of a leapfrog, and of
  * nbody_accel with xi == xj and no explicit shape -- with a potential the
- * same, except that the symmetric pass keeps four partials per particle, so
- * its block may grow earlier as the 16 GiB bound binds; op
+ * same shape, with four partials per particle in the symmetric pass; op
  * NB_OP_ADJOINT: the fused adjoint pass of nbody_step_adjoint). Host-side
  * only (no device needed). NB_EINVAL for another op, n outside 1..2^30 or a
  * NULL out; NB_EUNSUPPORTED for an unknown prec.
@@ -381,9 +380,9 @@ size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int s
  * block_particles = block * i_per_lane, one workgroup per block pair,
  * partials per block (FP32; FP64 for NB_F64) added in a fixed order
  * (NB_MIX_TILEC, and NB_F32 and NB_F64 for the force, from 12288 up to
- * 2^28 particles; the force's blocks grow from 2048 to 4096 particles while
- * every partial at once would pass 16 GiB, the adjoint's stay at 1024; the
- * partials are written and folded in bands of the workspace).
+ * 2^28 particles; from 2^18 the force takes blocks of 2048 particles and
+ * the adjoint blocks of 1024 at every n; the partials are written and
+ * folded in bands of the workspace).
  * symmetric = 0: the one-sided kernel in the shape (i_per_lane, block,
  * split).
  */

@@ -75,8 +75,8 @@ template <bool F> struct QRange {
 template <int K, bool JSIDE, bool F, class Sum>
 __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 (*rl)[128], float* jq,
                                           const float* xi, const float* yi, const float* zi,
-                                          const float* mi, const float* lxi, const float* lyi,
-                                          const float* lzi, Sum (*s)[NQ], float eps2,
+                                          const float* mi, const float* mi3, const float* lxi,
+                                          const float* lyi, const float* lzi, Sum (*s)[NQ], float eps2,
                                           int lane) {
     // groups of 64 sources stored twice in a row: lane l reads source
     // (l + t) mod 64 at rp[g][l + t] (see the force pass)
@@ -111,14 +111,16 @@ __device__ __forceinline__ void asym_tile(const float4 (*rp)[128], const float4 
                 const float uy = fmat(mi[k], lj.y, -(q.w * lyi[k]));
                 const float uz = fmat(mi[k], lj.z, -(q.w * lzi[k]));
                 const float dl = fmat(dz, lj.z, fmat(dy, lj.y, dx * lj.x));  // d . lam_j
-                float du, dli = 0.f;
-                if (JSIDE) {  // d . u = m_i (d . lam_j) - m_j (d . lam_i), both dots needed anyway
+                float e, dli = 0.f;
+                if (JSIDE) {
+                    // -3 d . u = (-3 m_i)(d . lam_j) - (-3 m_j)(d . lam_i): both dots are
+                    // needed anyway, and the factors -3 m come with the sink and the
+                    // source record
                     dli = fmat(dz, lzi[k], fmat(dy, lyi[k], dx * lxi[k]));
-                    du = fmat(mi[k], dl, -(q.w * dli));
+                    e = r2 * fmat(mi3[k], dl, -(lj.w * dli));
                 } else {
-                    du = fmat(dz, uz, fmat(dy, uy, dx * ux));
+                    e = (-3.f * r2) * fmat(dz, uz, fmat(dy, uy, dx * ux));
                 }
-                const float e = (-3.f * r2) * du;
                 const float tx = fmat(e, dx, ux);
                 const float ty = fmat(e, dy, uy);
                 const float tz = fmat(e, dz, uz);
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         }
         sink_block_origin<W>(cx, cy, cz, min(a.n - I * BI, BI), org, ox, oy, oz);
     }
-    float xi[K], yi[K], zi[K], mi[K], lxi[K], lyi[K], lzi[K];
+    float xi[K], yi[K], zi[K], mi[K], mi3[K], lxi[K], lyi[K], lzi[K];
     // the sink side: with two sinks per lane an FP32 sum per 64-source group
     // folded into FP64; with four (registers are short) an FP32 running sum
     // over the block, as the source side is
@@ -204,6 +206,7 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         yi[k] = ok ? float(a.y[i] - oy) : 0.f;
         zi[k] = ok ? float(a.z[i] - oz) : 0.f;
         mi[k] = ok ? a.m[i] : 0.f;  // a padding sink adds exactly 0 to the j side
+        mi3[k] = -3.f * mi[k];
         lxi[k] = ok ? float(a.lx[i]) : 0.f;
         lyi[k] = ok ? float(a.ly[i]) : 0.f;
         lzi[k] = ok ? float(a.lz[i]) : 0.f;
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
             if (j < je) {
                 p = make_float4(float(a.x[j] - ox), float(a.y[j] - oy), float(a.z[j] - oz),
                                 a.m[j]);
-                l = make_float4(float(a.lx[j]), float(a.ly[j]), float(a.lz[j]), 0.f);
+                l = make_float4(float(a.lx[j]), float(a.ly[j]), float(a.lz[j]), -3.f * a.m[j]);
             }
             rp[q >> 6][q & 63] = p;
             rp[q >> 6][(q & 63) + 64] = p;
@@ -230,11 +233,11 @@ __global__ __launch_bounds__(W * 64) void adjoint_sym_kernel(ASymArgs a) {
         }
         __syncthreads();
         if (jside)
-            asym_tile<K, true, F, Sum>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, lxi, lyi, lzi, s,
-                                  a.eps2, lane);
+            asym_tile<K, true, F, Sum>(rp, rl, &jacc[w][0][0], xi, yi, zi, mi, mi3, lxi, lyi, lzi,
+                                       s, a.eps2, lane);
         else
-            asym_tile<K, false, F, Sum>(rp, rl, nullptr, xi, yi, zi, mi, lxi, lyi, lzi, s, a.eps2,
-                                        lane);
+            asym_tile<K, false, F, Sum>(rp, rl, nullptr, xi, yi, zi, mi, mi3, lxi, lyi, lzi, s,
+                                        a.eps2, lane);
         __syncthreads();
         if (jside) {
             for (int q = tid; q < NQF * TJ; q += NT) {

@@ -452,10 +452,6 @@ hipError_t run_sym(const SymShape& sh, int64_t n, const void* x, const void* m, 
     return hipSuccess;
 }
 
-// Blocks grow while every partial of the pass at once would pass
-// kSymGrowBytes (larger blocks, fewer partials to write and read back).
-constexpr size_t kSymGrowBytes = size_t(16) << 30;
-
 }  // namespace
 
 bool sym_shape_supported(int prec, const SymShape& s) {
@@ -487,11 +483,13 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     //    211.7 for 4 x 4, 2^18: 13.16 against 13.56; FP64 (FP64 sums
     //    throughout) 2^20: 436.2 ms against 477.5 for 8 waves x 4, 2^18: 27.6
     //    against 28.0 for 4 x 4.
-    // From 2^18 the blocks grow to 4096 (eight waves) while every partial of
-    // the pass at once (nb * 3 * n values, or nb * 4 * n with the potential)
-    // would pass 16 GiB (2^21: 814.2 ms against 815.5 for blocks of 2048).
-    // The pass runs in bands when the workspace is smaller (SymLayout), so it
-    // serves every n up to 2^28.
+    // Blocks of 2048 at every n from 2^18: eight waves in blocks of 4096 halve
+    // the partials but gain nothing (2^21: 814.2 ms against 815.5), and with
+    // the potential (137 VGPRs, three waves per SIMD) a CU holds only one
+    // eight-wave workgroup (2^21 with the potential: 1024 ms in blocks of
+    // 4096, 835 in blocks of 2048). The partials (nb * 3 * n values, nb * 4 * n with the
+    // potential) are written and folded in bands of the workspace
+    // (SymLayout), so the pass serves every n up to 2^28 in bounded memory.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
@@ -503,11 +501,9 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
         static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
         return bi(small[1]) <= n / 48 ? small[1] : small[0];
     }
-    if (n < (int64_t(1) << 18)) return SymShape{4, 4};    // 1024
-    static const SymShape large[] = {{4, 8}, {8, 8}};  // 2048, 4096
-    int k = 0;
-    while (k < 1 && sym_full_bytes(sym_layout(prec, large[k], n, pot)) > kSymGrowBytes) ++k;
-    return large[k];
+    (void)pot;  // the potential takes the same shapes
+    if (n < (int64_t(1) << 18)) return SymShape{4, 4};  // 1024
+    return SymShape{4, 8};                               // 2048
 }
 
 hipError_t launch_force_sym(int prec, const SymShape& sh, int64_t n, const void* x,

@@ -68,8 +68,7 @@ def test_workspace_size(L):
     # a set acting on itself with the tile-compensated policy from 12288 on:
     # the symmetric pass, one FP32 partial per particle, component and block
     # (blocks of at most min(n/48, 512) particles below 2^17, 1024 up to 2^18,
-    # 2048 from there, larger while every partial at once would pass 16 GiB);
-    # the whole set of partials up to 4 GiB
+    # 2048 from there); the whole set of partials up to 4 GiB
     assert L.nbody_workspace_size(1, 12288, TILEC) == 48 * 3 * 12288 * 4
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
     assert L.nbody_workspace_size(1, 24576, TILEC) == 48 * 3 * 24576 * 4
@@ -82,10 +81,10 @@ def test_workspace_size(L):
     for n in (1 << 20, 1 << 21, 3 << 20, 5 << 20):
         assert L.nbody_workspace_size(1, n, TILEC) == 3 * n * 8 + G4, n
     # ... or one row of blocks per band where a row needs more (2^28: blocks
-    # of 4096, a row holds the slot of every particle and the 65535 other
-    # slots of its own 4096)
+    # of 2048, a row holds the slot of every particle and the 131071 other
+    # slots of its own 2048)
     n = 1 << 28
-    assert L.nbody_workspace_size(1, n, TILEC) == 3 * n * 8 + 3 * 4 * (n + 65535 * 4096)
+    assert L.nbody_workspace_size(1, n, TILEC) == 3 * n * 8 + 3 * 4 * (n + 131071 * 2048)
     # FP32: FP32 running sums; FP64: FP64 partials
     assert L.nbody_workspace_size(1, 1 << 20, F32) == 3 * (1 << 20) * 4 + G4
     assert L.nbody_workspace_size(1, 1 << 20, F64) == 3 * (1 << 20) * 8 + G4
@@ -287,17 +286,17 @@ def test_pass_info(L):
     assert info.symmetric == 0 and info.block_particles == 0 and info.split >= 1
     assert L.nbody_pass_info(1, 1 << 18, TILEC, ctypes.byref(info)) == 0
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 8, 2048)
-    # FP64: the same shapes, FP64 partials (blocks of 4096 from 2^21)
+    # FP64: the same shapes, FP64 partials
     assert L.nbody_pass_info(1, 1 << 17, F64, ctypes.byref(info)) == 0
     assert (info.i_per_lane, info.block_particles) == (4, 1024)
     assert L.nbody_pass_info(1, 1 << 20, F64, ctypes.byref(info)) == 0
     assert (info.symmetric, info.i_per_lane, info.block_particles) == (1, 8, 2048)
     assert info.workspace_bytes == 3 * (1 << 20) * 8 + (4 << 30)
     assert L.nbody_pass_info(1, 1 << 21, F64, ctypes.byref(info)) == 0
-    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 512, 8, 4096)
-    # the symmetric passes serve every size up to 2^28: blocks of 4096
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 8, 2048)
+    # the symmetric passes serve every size up to 2^28: blocks of 2048
     # (force) and 1024 (adjoint) at the top
-    for op, b in ((1, 4096), (2, 1024)):
+    for op, b in ((1, 2048), (2, 1024)):
         assert L.nbody_pass_info(op, 1 << 28, TILEC, ctypes.byref(info)) == 0
         assert (info.symmetric, info.block_particles) == (1, b)
     assert L.nbody_pass_info(1, (1 << 28) + 1, TILEC, ctypes.byref(info)) == 0

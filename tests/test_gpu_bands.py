@@ -174,7 +174,7 @@ def test_full_size_default_workspace_bitwise():
 
 
 def test_beyond_one_band_of_partials():
-    """2^22 particles: the force pass (blocks of 4096, 52 GB of partials in
+    """2^22 particles: the force pass (blocks of 2048, 103 GB of partials in
     all) and a fused adjoint pass (blocks of 1024, 481 GB in all) in bands of
     4 GiB; sampled rows against the oracle, and the third law on the force."""
     from nbody_inputs import plummer_positions_device
