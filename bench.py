@@ -52,12 +52,13 @@ FLOP_PER_INTERACTION_ADJOINT = 55
 #   force, one-sided: 3 sub, 3 FMA (s), 3 mul (r^3 m_j), 3 FMA (sum) = 20
 #   force, symmetric: + 1 mul (r^3 m_i) + 3 FMA (source side) = 27
 #   adjoint, one-sided with the force sums: 55 (without them: 48)
-#   adjoint, symmetric with the force sums: 73 (without them: 59): the one-
-#     sided body + d.lam_i (5) - 2 for d.u from the two dots + the source
-#     side (1 mul + 7 FMA with the force sums, 4 FMA without)
+#   adjoint, symmetric with the force sums: 72 (without them: 58): the one-
+#     sided body + d.lam_i (5) - 2 for d.u from the two dots - 1 for the
+#     factor -3 that comes with the masses + the source side (1 mul + 7 FMA
+#     with the force sums, 4 FMA without)
 EXEC_FLOP = {("force", False): 20, ("force", True): 27,
              ("adjoint", False, True): 55, ("adjoint", False, False): 48,
-             ("adjoint", True, True): 73, ("adjoint", True, False): 59}
+             ("adjoint", True, True): 72, ("adjoint", True, False): 58}
 
 
 def pair_evaluations(n, info):

@@ -53,8 +53,8 @@ def test_executed_work_counts():
         full, tail = divmod(n, b)
         assert one == full * b * b + tail * tail
         assert bench.executed_flop("force", n, info) == 27 * off + 20 * one
-        assert bench.executed_flop("adjoint", n, info, True) == 73 * off + 55 * one
-        assert bench.executed_flop("adjoint", n, info, False) == 59 * off + 48 * one
+        assert bench.executed_flop("adjoint", n, info, True) == 72 * off + 55 * one
+        assert bench.executed_flop("adjoint", n, info, False) == 58 * off + 48 * one
     one_sided = {"symmetric": 0, "block_particles": 0}
     assert bench.pair_evaluations(1000, one_sided) == (0.0, 1e6)
     assert bench.executed_flop("adjoint", 1000, one_sided, False) == 55e6
