@@ -6,10 +6,10 @@
 //   to i:  m_j s^-3/2 d,   T(d) u,    s^-3/2 (lam_j . d)
 //   to j: -m_i s^-3/2 d,  -T(d) u,   -s^-3/2 (lam_i . d)
 // (T is even in d and u is odd under the swap), so one reciprocal square
-// root, one T(d) u and one s^-3/2 serve both ends: 43 VALU + 1 rsqrt per
+// root, one T(d) u and one s^-3/2 serve both ends: 42 VALU + 1 rsqrt per
 // pair (d . u comes from the two dot products with lam_i and lam_j, which
-// the mass adjoints need anyway), i.e. 21.5 VALU + 1/2 rsqrt per
-// interaction against 34 + 1 one-sided.
+// the mass adjoints need anyway, and the factor -3 of T with the masses),
+// i.e. 21 VALU + 1/2 rsqrt per interaction against 34 + 1 one-sided.
 // The blocking, the work items (block pairs I <= J), the origin of the pair
 // arithmetic (the centroid of block I), the source-side sums carried through
 // the lanes and the fixed-order FP32 partials are those of the symmetric
@@ -361,10 +361,11 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     //    in blocks of at most n/64 (256 or 512 particles; 65536: 4 waves x 2,
     //    2.33 ms, within 1 % of the fastest shape);
     //  * from 2^18 four sinks per lane with FP32 block sums on the sink side
-    //    (154 VGPRs, 3 waves per SIMD) in 4-wave blocks of 1024 at every n:
+    //    (158 VGPRs with the force sums, 3 waves per SIMD; 125 and 4 waves
+    //    without them) in 4-wave blocks of 1024 at every n:
     //    half the LDS reads and source-side rotations per pair -- 2^20: 542
     //    ms against 561 for 8 waves x 2; 2^21: 2165 ms against 2406 for 8
-    //    waves x 4 (blocks of 2048: half the partials, but with 154 VGPRs a
+    //    waves x 4 (blocks of 2048: half the partials, but with 158 VGPRs a
     //    CU holds one eight-wave workgroup, two waves per SIMD, against three
     //    four-wave ones). The partials (nb * 7 * n floats, 60 GB at 2^20) are
     //    written and read back in bands of the workspace (SymLayout), so the

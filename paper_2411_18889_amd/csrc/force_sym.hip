@@ -16,7 +16,9 @@
 //    every 64-source group lane l meets source (l + t) mod 64 at step t, so
 //    the 64 lanes touch 64 different sources at every step. The i side is a
 //    running FP32 sum folded into FP64 after each group (as the tile-
-//    compensated policy); the j-side sum of a source travels with it through
+//    compensated policy) where a lane holds up to four sinks, and an FP32
+//    sum over the whole source block, as the j side's, where it holds eight
+//    (registers are short); the j-side sum of a source travels with it through
 //    the lanes (a one-lane rotation per step through the LDS crossbar), so
 //    after the 64 steps of a group it is back in the lane that owns the
 //    source, which writes it to the wave's LDS row. At the end of a tile the
@@ -483,13 +485,14 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     //    211.7 for 4 x 4, 2^18: 13.16 against 13.56; FP64 (FP64 sums
     //    throughout) 2^20: 436.2 ms against 477.5 for 8 waves x 4, 2^18: 27.6
     //    against 28.0 for 4 x 4.
-    // Blocks of 2048 at every n from 2^18: eight waves in blocks of 4096 halve
-    // the partials but gain nothing (2^21: 814.2 ms against 815.5), and with
-    // the potential (137 VGPRs, three waves per SIMD) a CU holds only one
-    // eight-wave workgroup (2^21 with the potential: 1024 ms in blocks of
-    // 4096, 835 in blocks of 2048). The partials (nb * 3 * n values, nb * 4 * n with the
-    // potential) are written and folded in bands of the workspace
-    // (SymLayout), so the pass serves every n up to 2^28 in bounded memory.
+    // Blocks of 2048 at every n from 2^18: eight waves in blocks of 4096
+    // halve the partials but gain nothing (2^21: 814.2 ms against 815.5),
+    // and with the potential (137 VGPRs, three waves per SIMD) a CU holds
+    // only one eight-wave workgroup (2^21 with the potential: 1024 ms in
+    // blocks of 4096, 835 in blocks of 2048). The partials (nb * 3 * n
+    // values, nb * 4 * n with the potential) are written and folded in bands
+    // of the workspace (SymLayout), so the pass serves every n up to 2^28 in
+    // bounded memory.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
     // finishing kernel's loads overlapped: one-sided 19 % faster at 8192;
     // symmetric 23 % faster at 12288, 37 % at 24576).
