@@ -142,7 +142,8 @@ CSRC = os.path.join(ROOT, "paper_2411_18889_amd", "csrc")
 KERNEL_SOURCES = {"force_kernel": ["common.h", "force.hip"],
                   "force_sym_kernel": ["common.h", "force_sym.hip"],
                   "adjoint_kernel": ["common.h", "adjoint.hip"],
-                  "adjoint_sym_kernel": ["common.h", "adjoint_sym.hip"],
+                  "adjoint_sym_kernel": ["common.h", "adjoint_sym.hip", "adjoint_sym_pairs.h",
+                                         "adjoint_sym_entry.hip"],
                   "diffusion_kernel4": ["common.h", "diffusion.hip"]}
 
 

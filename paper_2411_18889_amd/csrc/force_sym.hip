@@ -48,6 +48,12 @@
 //    structure) and FP64 (FP64 records, pair arithmetic, source-side sums,
 //    partials and slot sums; the source-side sums rotate as two 32-bit
 //    halves). The description above says FP32 where it is the pair type.
+//
+// The build compiles this file with LLVM's iterative ILP scheduling strategy
+// (-mllvm -amdgpu-sched-strategy=iterative-ilp), measured against the default
+// on one box: tile-compensated 2^20 186.0 against 188.9 ms (with the
+// potential 206.7 against 207.9), plain FP32 186.4 against 188.8, 262144 12.10
+// against 12.23 ms, FP64 and 65536 unchanged.
 #include "common.h"
 
 namespace nb {
