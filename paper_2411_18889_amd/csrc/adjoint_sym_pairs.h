@@ -24,13 +24,6 @@ struct ASymArgs {
     float* part;  // the band's partials (SymBandView::offset)
 };
 
-// Lane l receives the value of lane (l + 1) mod 64, through the LDS
-// crossbar (ds_bpermute; see the force pass).
-__device__ __forceinline__ float from_next_lane(float v) {
-    const int src = ((__lane_id() + 1) & 63) << 2;  // byte address of the source lane
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
-}
-
 // F: also accumulate the force a (quantities 0..2); without it (a pass whose
 // state comes from a checkpoint, not from walking back) the quantities are
 // 3..6 only: 8 VALU, three rotations and three partial rows less per pair.

@@ -113,24 +113,6 @@ struct SymFinishArgs {
     double dt;
 };
 
-// Lane l receives the value of lane (l + 1) mod 64, through the LDS
-// crossbar (ds_bpermute): measured 14 % faster for the force pass and 10 %
-// for the adjoint than the same rotation on the vector ALU (DPP wave_rol:1),
-// whose moves cost about four VALU issue slots each and sit in the
-// accumulation chains; the crossbar is otherwise idle here.
-__device__ __forceinline__ float from_next_lane(float v) {
-    const int src = ((__lane_id() + 1) & 63) << 2;  // byte address of the source lane
-    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
-}
-
-// The same for a double: its two 32-bit halves travel separately.
-__device__ __forceinline__ double from_next_lane(double v) {
-    const int src = ((__lane_id() + 1) & 63) << 2;
-    const int lo = __builtin_amdgcn_ds_bpermute(src, __double2loint(v));
-    const int hi = __builtin_amdgcn_ds_bpermute(src, __double2hiint(v));
-    return __hiloint2double(hi, lo);
-}
-
 // One tile of sources against the K sinks of this lane. The tile is held as
 // TJ/64 groups of 64 sources, each stored twice in a row (rec[g][0..127]), so
 // that lane l meets source (l + t) mod 64 of the group at step t by reading
