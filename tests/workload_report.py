@@ -240,6 +240,13 @@ def pass_scan():
                                  inner)
                 ainfo = nb.pass_info(2, n, prec)
                 row["adj_" + prec] = (ms, bench.executed_flop("adjoint", n, ainfo, True) / (ms * 1e-3) / peak)
+                if prec == "mix_tilec":
+                    # the entry pass of a walk (no force sums), the kind every
+                    # pass of a walk over per-step checkpoints is
+                    ms = timed_batch(lambda: nb.step_adjoint(st[0], st[1], M, st[2], st[3], st[4], st[5],
+                                                             eps, 2.0 ** -16, 0, prec=prec,
+                                                             entry_half=True, workspace=wsa), inner)
+                    row["adj0"] = (ms, bench.executed_flop("adjoint", n, ainfo, False) / (ms * 1e-3) / peak)
         out.append(row)
     return out
 
@@ -292,12 +299,14 @@ def main():
               "x0 %.2g, v0 %.2g, m %.2g" % (f, b, b / f, *errs))
     if not args.skip_scan:
         print("\nPass times across N (Plummer, eps = 2^-9; force = `nbody_accel` of the set on itself, "
-              "adjoint = one reverse step of `nbody_step_adjoint`, resident inputs and workspace; "
+              "adjoint step = one reverse step of `nbody_step_adjoint` (a pass with the force sums), "
+              "adjoint entry pass = the entry pass of a walk (no force sums; every pass of a walk over "
+              "per-step checkpoints is of this kind), resident inputs and workspace; "
               "best of 3 batches of 50 (up to 16384), 10, 3, then 1 back-to-back calls; "
               "ms per call, % of the FP32 (FP64) vector peak from executed flop)\n")
         print("| N | force tile-compensated | force + potential tile-compensated | adjoint step tile-compensated "
-              "| force FP32 | force FP64 | adjoint step FP64 |")
-        print("|---:|---|---|---|---|---|---|")
+              "| adjoint entry pass tile-compensated | force FP32 | force FP64 | adjoint step FP64 |")
+        print("|---:|---|---|---|---|---|---|---|")
         for r in pass_scan():
             def cell(k):
                 if k not in r:
@@ -305,9 +314,9 @@ def main():
                 ms, frac = r[k]
                 g = "%.4g ms (%.0f G/s" % (ms, r["n"] ** 2 / ms / 1e6)
                 return g + (", %.0f %%)" % (100 * frac) if frac is not None else ")")
-            print("| %d | %s | %s | %s | %s | %s | %s |" % (
-                r["n"], cell("force_mix_tilec"), cell("pot"), cell("adj_mix_tilec"), cell("force_f32"),
-                cell("force_f64"), cell("adj_f64")))
+            print("| %d | %s | %s | %s | %s | %s | %s | %s |" % (
+                r["n"], cell("force_mix_tilec"), cell("pot"), cell("adj_mix_tilec"), cell("adj0"),
+                cell("force_f32"), cell("force_f64"), cell("adj_f64")))
     if not args.skip_cpu:
         rows, k0 = cpu_table()
         print("\nFP64 oracle (`oracle_accel`) on the host: Ginteractions/s (sampled sinks x all N)\n")
