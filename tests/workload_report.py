@@ -281,16 +281,25 @@ def main():
     print("| workload | N | precision | pass | force pass | Ginteractions/s | % peak executed (20-flop convention) "
           "| e_glob | p99 | max | dE over the steps | reference dE | positions vs FP64 run |")
     print("|---|---:|---|---|---:|---:|---|---|---|---|---|---|---|")
-    for name in args.only:
-        if name == "adjoint-16384":
-            continue
-        log("workload", name)
-        w, n, rows, ref = workload_rows(name)
-        for r in rows:
-            print("| %s | %d | %s | %s | %.4g ms | %.0f | %.1f %% (%.1f %%) | %.2g | %.2g | %.2g | %.4e | %s | %s |"
-                  % (name, n, r["prec"], r["pass"], r["ms"], r["gint"], 100 * r["frac"],
-                     100 * r["frac_conv"], r["e"], r["p99"], r["max"], r["dE"], ref,
-                     "%.2g of the distance travelled" % r["dx"] if "dx" in r else "—"))
+    bench = _bench()
+
+    def clock_line(clk):
+        c = clk.summary()
+        return ("\nMean shader clock while these were measured: %.0f MHz (%.0f-%.0f; the peaks assume "
+                "2400)" % (c["sclk_mhz_mean"], c["sclk_mhz_min"], c["sclk_mhz_max"])) if c else ""
+
+    with bench.ClockSampler() as clk:
+        for name in args.only:
+            if name == "adjoint-16384":
+                continue
+            log("workload", name)
+            w, n, rows, ref = workload_rows(name)
+            for r in rows:
+                print("| %s | %d | %s | %s | %.4g ms | %.0f | %.1f %% (%.1f %%) | %.2g | %.2g | %.2g | %.4e | %s | %s |"
+                      % (name, n, r["prec"], r["pass"], r["ms"], r["gint"], 100 * r["frac"],
+                         100 * r["frac_conv"], r["e"], r["p99"], r["max"], r["dE"], ref,
+                         "%.2g of the distance travelled" % r["dx"] if "dx" in r else "—"))
+    print(clock_line(clk))
     if "adjoint-16384" in args.only:
         log("workload adjoint-16384")
         f, b, errs = adjoint_row()
@@ -307,7 +316,9 @@ def main():
         print("| N | force tile-compensated | force + potential tile-compensated | adjoint step tile-compensated "
               "| adjoint entry pass tile-compensated | force FP32 | force FP64 | adjoint step FP64 |")
         print("|---:|---|---|---|---|---|---|---|")
-        for r in pass_scan():
+        with bench.ClockSampler() as clk:
+            scan = pass_scan()
+        for r in scan:
             def cell(k):
                 if k not in r:
                     return "—"
@@ -317,6 +328,7 @@ def main():
             print("| %d | %s | %s | %s | %s | %s | %s | %s |" % (
                 r["n"], cell("force_mix_tilec"), cell("pot"), cell("adj_mix_tilec"), cell("adj0"),
                 cell("force_f32"), cell("force_f64"), cell("adj_f64")))
+        print(clock_line(clk))
     if not args.skip_cpu:
         rows, k0 = cpu_table()
         print("\nFP64 oracle (`oracle_accel`) on the host: Ginteractions/s (sampled sinks x all N)\n")
