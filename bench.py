@@ -359,19 +359,16 @@ def traffic_summary(args):
                     "counters' reading); regenerate when the kernel's sources change"
                     % (f_factor, w_factor),
            "commands": ["cd /tmp && export TMPDIR=/tmp; from the repository root, one counter C "
-                        "per run, C in FETCH_SIZE WRITE_SIZE:",
-                        "rocprofv3 --pmc C -d gpurun_out/pmc_C -o bench --output-format csv -- "
-                        "python3 bench.py --steps 1 --warmup 0 --rollout %d --cpu-sample 0" % args.rollout,
-                        "rocprofv3 --pmc C -d gpurun_out/pmc_diff_C -o diff --output-format csv -- "
+                        "per run, C in FETCH_SIZE WRITE_SIZE, each run into a folder of its own "
+                        "(the folders of each entry are in its 'counter_folders'):",
+                        "rocprofv3 --pmc C -d <folder> -o bench --output-format csv -- "
+                        "python3 bench.py --steps 1 --warmup 0 --rollout R --cpu-sample 0",
+                        "rocprofv3 --pmc C -d <folder> -o diff --output-format csv -- "
                         "python3 bench.py --workload diffusion-512 --steps 1 --warmup 1 --cpu-sample 0",
-                        "rocprofv3 --pmc C -d gpurun_out/pmc_copy_C -o copy --output-format csv -- "
+                        "rocprofv3 --pmc C -d <folder> -o copy --output-format csv -- "
                         "python3 bench.py --copy-probe-mib 1024",
-                        "python3 bench.py --rollout %d --traffic-from gpurun_out/pmc_FETCH_SIZE "
-                        "gpurun_out/pmc_WRITE_SIZE gpurun_out/pmc_copy_FETCH_SIZE "
-                        "gpurun_out/pmc_copy_WRITE_SIZE" % args.rollout,
-                        "python3 bench.py --workload diffusion-512 --traffic-from "
-                        "gpurun_out/pmc_diff_FETCH_SIZE gpurun_out/pmc_diff_WRITE_SIZE "
-                        "gpurun_out/pmc_copy_FETCH_SIZE gpurun_out/pmc_copy_WRITE_SIZE"]}
+                        "python3 bench.py [--workload W] --rollout R --traffic-from <FETCH_SIZE folder> "
+                        "<WRITE_SIZE folder> <copy FETCH_SIZE folder> <copy WRITE_SIZE folder>"]}
     for fam, names in TRAFFIC_KERNELS.items():
         fk = sum(v for k, v in fetch if _kernel_base(k) in names)
         wk = sum(v for k, v in write if _kernel_base(k) in names)
@@ -385,7 +382,9 @@ def traffic_summary(args):
             "bytes_per_launch": (fk * 1024.0 * f_factor + wk * 1024.0 * w_factor) / passes,
             "fetch_bytes_per_pass": fk * 1024.0 * f_factor / passes,
             "write_bytes_per_pass": wk * 1024.0 * w_factor / passes,
-            "pair_kernel_dispatches": nd, "passes": passes}
+            "pair_kernel_dispatches": nd, "passes": passes,
+            "counter_folders": list(args.traffic_from),
+            **({} if fam == "diffusion_kernel4" else {"rollout": args.rollout})}
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     old = {}
     if os.path.exists(path):
