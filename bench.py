@@ -110,7 +110,7 @@ def adjoint_schedule(R, K):
     return R - anchors, 1 + anchors
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -135,7 +135,9 @@ def parse():
                     help="no GPU: turn four rocprofv3 --pmc output folders (FETCH_SIZE and "
                          "WRITE_SIZE of a run of this benchmark with --rollout R, and of "
                          "--copy-probe-mib 1024) into profiles/hbm_traffic.json")
-    return ap.parse_args()
+    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"),
+                    help="the summary --traffic-from writes (entries of other workloads kept)")
+    return ap.parse_args(argv)
 
 
 CSRC = os.path.join(ROOT, "paper_2411_18889_amd", "csrc")
@@ -385,7 +387,7 @@ def traffic_summary(args):
             "pair_kernel_dispatches": nd, "passes": passes,
             "counter_folders": list(args.traffic_from),
             **({} if fam == "diffusion_kernel4" else {"rollout": args.rollout})}
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    path = args.traffic_out
     old = {}
     if os.path.exists(path):
         with open(path) as fh:

@@ -61,3 +61,42 @@ def test_executed_work_counts():
     assert bench.adjoint_schedule(10, 20) == (9, 2)
     assert bench.adjoint_schedule(200, 20) == (190, 11)
     assert bench.adjoint_schedule(3, 1) == (0, 4)
+
+
+def _write_pmc(folder, counter, rows):
+    """A rocprofv3 --pmc CSV with one row per (kernel name, value)."""
+    import csv
+    os.makedirs(folder, exist_ok=True)
+    with open(os.path.join(folder, "run_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (k, v) in enumerate(rows):
+            w.writerow([i, k, counter, v])
+
+
+def test_traffic_summary_from_counter_folders(tmp_path):
+    """--traffic-from: FETCH_SIZE scaled by what a 1 GiB copy reads (here half
+    of it, so x2), WRITE_SIZE by what it writes (x1), the pair kernel's and
+    its fold kernel's dispatches summed and divided by the R + 1 passes."""
+    import bench
+    gib_kib = float(1 << 20)
+    _write_pmc(tmp_path / "cf", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", gib_kib / 2)])
+    _write_pmc(tmp_path / "cw", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", gib_kib)])
+    k = "void nb::asym::adjoint_sym_kernel<4, 4, false>(nb::asym::ASymArgs)"
+    f = "void nb::(anonymous namespace)::adjoint_sym_finish_kernel<false>(nb::ASymFinishArgs)"
+    other = "void nb::(anonymous namespace)::pe_pairs_kernel<double, float>(double const*)"
+    # R = 3: 4 passes of 2 bands each
+    _write_pmc(tmp_path / "f", "FETCH_SIZE", [(k, 100.0)] * 8 + [(f, 50.0)] * 8 + [(other, 1e6)])
+    _write_pmc(tmp_path / "w", "WRITE_SIZE", [(k, 30.0)] * 8 + [(f, 10.0)] * 8 + [(other, 1e6)])
+    out = tmp_path / "traffic.json"
+    args = bench.parse(["--rollout", "3", "--traffic-out", str(out), "--traffic-from",
+                        str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"),
+                        str(tmp_path / "cw")])
+    bench.traffic_summary(args)
+    import json
+    rec = json.loads(out.read_text())["adjoint_sym_kernel@scale-2^20"]
+    assert rec["passes"] == 4 and rec["pair_kernel_dispatches"] == 8
+    assert rec["fetch_bytes_per_pass"] == (8 * 100 + 8 * 50) * 1024 * 2.0 / 4
+    assert rec["write_bytes_per_pass"] == (8 * 30 + 8 * 10) * 1024 * 1.0 / 4
+    assert rec["bytes_per_launch"] == rec["fetch_bytes_per_pass"] + rec["write_bytes_per_pass"]
+    assert rec["source_sha256"] == bench.kernel_source_hash("adjoint_sym_kernel")
