@@ -23,9 +23,10 @@ PREC = "mix_tilec"
 TOL = 1e-5
 TOLS = {"f32": 1e-5, "f64": 1e-12}
 
-# blocks of 256 (12288 .. 24575), 512 and 1024; ragged last blocks and tiles
+# blocks of 256 (12288 .. 24575), 512, 1024 and 2048 (eight sinks per lane,
+# from 2^18); ragged last blocks and tiles
 SYM_NS = (12288, 12289, 14000, 16384, 16385, 20000, 24576 + 7, 32768, 32769, 32768 + 255, 40000, 65535, 65536,
-          65536 + 1000, 131072 + 77)
+          65536 + 1000, 131072 + 77, 262144 + 1, 262144 + 2047)
 
 
 def _classic(xd, md, eps):
@@ -58,7 +59,8 @@ def test_sym_matches_oracle_and_one_sided(n):
 
 
 @pytest.mark.parametrize("prec,n", [(p, n) for p in ("f32", "f64")
-                                    for n in (12288, 12289, 20000, 40000, 65535, 65536 + 1000)])
+                                    for n in (12288, 12289, 20000, 40000, 65535, 65536 + 1000,
+                                              262144 + 2047)])
 def test_sym_f32_f64_policies(prec, n):
     """The plain FP32 policy (FP32 state, every sum FP32) and the FP64 one
     (FP64 pair arithmetic, FP64 source-side sums through the lanes, FP64
