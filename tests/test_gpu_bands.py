@@ -47,7 +47,7 @@ def _ws(nbytes):
 
 
 @pytest.mark.parametrize("prec", ("mix_tilec", "f32", "f64"))
-@pytest.mark.parametrize("n", (12289, 40000, 65536 + 1000))
+@pytest.mark.parametrize("n", (12289, 40000, 65536 + 1000, 262144 + 999))
 def test_force_bands_bitwise(prec, n):
     x, v, m = plummer_sphere(n, 700 + n % 11)
     m = m * np.random.default_rng(n).uniform(0.5, 1.5, size=n)
