@@ -95,10 +95,12 @@ def test_step_bands_bitwise(prec):
     assert rel(host(out[0][2]), ao) <= (1e-12 if prec == "f64" else 1e-5)
 
 
-def test_adjoint_bands_bitwise():
+@pytest.mark.parametrize("n", (40000 + 77, 262144 + 77))
+def test_adjoint_bands_bitwise(n):
     """A three-step reverse walk (entry pass without the force sums, walked-
-    back passes with them, reverse drifts fused into the folds)."""
-    prec, n, S = "mix_tilec", 40000 + 77, 3
+    back passes with them, reverse drifts fused into the folds), with two
+    sinks per lane (40077) and four (262221, blocks of 1024)."""
+    prec, S = "mix_tilec", 3
     x, v, m = plummer_sphere(n, 744)
     eps, dt = 2.0 ** -8, 2.0 ** -9
     lam = np.random.default_rng(5).normal(size=(3, n))
