@@ -76,9 +76,10 @@ def test_noalloc_separate_sets():
 
 
 def test_noalloc_bands_within_its_scratch():
-    """262144 particles on themselves: 805 MB of partials in the symmetric
-    pass, which nbody_accel runs in one band; the no-alloc entry point runs
-    it in bands within its 128 MiB, bitwise the same."""
+    """262144 particles on themselves: 402 MB of partials in the symmetric
+    pass (eight sinks per lane, blocks of 2048), which nbody_accel runs in
+    one band; the no-alloc entry point runs it in bands within its 128 MiB,
+    bitwise the same."""
     n, prec, eps = 262144, "mix_tilec", 2.0 ** -9
     assert nb.pass_info(1, n, prec)["workspace_bytes"] > (128 << 20)
     x, v, m = plummer_sphere(n, 33)
