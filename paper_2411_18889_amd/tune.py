@@ -10,7 +10,9 @@ for every pair pass of the library, in the launch parameters of each:
   workgroup and sinks per lane;
 * the fused adjoint pass (``--op adjoint``): the same two families through
   ``nbody_step_adjoint_ex``, timed on one step of the reverse walk (a pass
-  that also sums a(x), as every walked-back step does).
+  that also sums a(x), as every walked-back step does) or, with
+  ``--adjoint-pass entry``, on the entry pass (no force sums, as every pass
+  of a walk over per-step checkpoints).
 
 For every (N, precision) it times each shape on a seeded Plummer sphere with
 the workspace the library asks for that shape, checks that each shape
