@@ -127,18 +127,23 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // Measured on MI355X with the tuner (tune.py; a walked-back step, the
     // pass with the force sums, and the entry pass without them; the run
     // these figures come from is in profiles/launch_shape_tuning.md):
-    //  * below 2^18 particles two sinks per lane -- the seven running sums per
-    //    sink, each an FP32 group sum folded into FP64, take ~126 VGPRs --
-    //    in blocks of at most n/64 (256 or 512 particles; 65536: 4 waves x 2,
-    //    2.33 ms, within 1 % of the fastest shape);
-    //  * from 2^18 four sinks per lane with FP32 block sums on the sink side
-    //    (158 VGPRs with the force sums, 3 waves per SIMD; 125 and 4 waves
-    //    without them) in 4-wave blocks of 1024 at every n:
+    //  * below 163840 particles two sinks per lane -- the seven running sums
+    //    per sink, each an FP32 group sum folded into FP64, take ~126 VGPRs
+    //    -- in blocks of at most n/64 (256 or 512 particles; 65536: 4 waves x
+    //    2, 2.33 ms, within 1 % of the fastest shape; 131072: the entry pass
+    //    6.55 ms against 6.70 for the best shape with four sinks, the
+    //    walked-back pass 8.96 against 8.57);
+    //  * from 163840 four sinks per lane with FP32 block sums on the sink
+    //    side (158 VGPRs with the force sums, 3 waves per SIMD; 159 and 3
+    //    waves without them, as scheduled in their own translation unit) in
+    //    4-wave blocks of 1024 at every n (163840: 10.39 / 13.20 ms against
+    //    10.50 / 14.06 for 4 x 2, entry / walked-back pass; 196608: 14.74 /
+    //    18.77 against 15.17 / 19.95):
     //    half the LDS reads and source-side rotations per pair -- 2^20: 542
     //    ms against 561 for 8 waves x 2; 2^21: 2165 ms against 2406 for 8
     //    waves x 4 (blocks of 2048: half the partials, but with 158 VGPRs a
     //    CU holds one eight-wave workgroup, two waves per SIMD, against three
-    //    four-wave ones). The partials (nb * 7 * n floats, 60 GB at 2^20) are
+    //    four-wave ones). The partials (nb * 7 * n floats, 30 GB at 2^20) are
     //    written and read back in bands of the workspace (SymLayout), so the
     //    pass serves every n up to 2^28 in bounded memory.
     // Below 12288 particles the one-sided kernel is faster (measured, with the
@@ -146,7 +151,7 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // symmetric 12 % faster at 12288, 21 % at 24576).
     if (prec != NB_MIX_TILEC || n < 48 * 256 || n > (int64_t(1) << 28)) return SymShape{0, 0};
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
-    if (n < (int64_t(1) << 18)) {
+    if (n < 163840) {
         static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
         return (bi(small[1]) <= n / 64) ? small[1] : small[0];
     }

@@ -461,11 +461,12 @@ SymLayout sym_layout(int prec, const SymShape& s, int64_t n, bool pot) {
 SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
     // Measured on MI355X with the tuner (tune.py; the run these figures come
     // from is in profiles/launch_shape_tuning.md), from 16384 to 2^21:
-    //  * below 2^17 particles two sinks per lane in blocks of at most n/48
+    //  * below 81920 particles two sinks per lane in blocks of at most n/48
     //    (>= 1176 equal work items for the 256 CUs): 256, or 512 from 24576
     //    (65536: 0.954 ms, the fastest shape 0.948);
-    //  * from 2^17 four-wave workgroups with four sinks per lane, blocks of
-    //    1024 (131072: 3.47 ms, the fastest symmetric shape);
+    //  * from 81920 four-wave workgroups with four sinks per lane, blocks of
+    //    1024 (81920: 1.292 against 1.347 ms for 4 x 2; 114688: 2.426 against
+    //    2.580; 131072: 3.47 ms, the fastest symmetric shape);
     //  * from 2^18 four waves with eight sinks per lane, blocks of 2048: one
     //    LDS record read and three source-side rotations per eight pairs, and
     //    with FP32 block sums on the sink side 120 VGPRs (4 waves per SIMD)
@@ -488,7 +489,7 @@ SymShape choose_sym_shape(int prec, int64_t n, bool pot) {
         n > (int64_t(1) << 28))
         return SymShape{0, 0};
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
-    if (n < (int64_t(1) << 17)) {
+    if (n < 81920) {
         static const SymShape small[] = {{2, 2}, {4, 2}};  // 256, 512
         return bi(small[1]) <= n / 48 ? small[1] : small[0];
     }
