@@ -67,7 +67,7 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(2, 4096, TILEC) > 0
     # a set acting on itself with the tile-compensated policy from 12288 on:
     # the symmetric pass, one FP32 partial per particle, component and block
-    # (blocks of at most min(n/48, 512) particles below 2^17, 1024 up to 2^18,
+    # (blocks of at most min(n/48, 512) particles below 81920, 1024 up to 2^18,
     # 2048 from there); the whole set of partials up to 4 GiB
     assert L.nbody_workspace_size(1, 12288, TILEC) == 48 * 3 * 12288 * 4
     assert L.nbody_workspace_size(1, 16384, TILEC) == 64 * 3 * 16384 * 4
@@ -100,7 +100,7 @@ def test_workspace_size(L):
     assert L.nbody_workspace_size(0, 1 << 30, TILEC) == (1 << 24) * 4 * 8
     assert L.nbody_workspace_size(0, 1 << 30, F64) == (1 << 24) * 4 * 8
     # and the symmetric adjoint pass: seven FP32 partials per particle and
-    # block (blocks of min(n/64, 512) below 2^18, 1024 from there at every
+    # block (blocks of min(n/64, 512) below 163840, 1024 from there at every
     # n), all of them up to 4 GiB, then seven FP64 running sums and bands of
     # about 4 GiB
     assert L.nbody_workspace_size(2, 12288, TILEC) == 48 * 7 * 12288 * 4

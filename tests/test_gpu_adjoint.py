@@ -98,12 +98,13 @@ def test_adjoint_symmetric_pass_matches_oracle(n):
     assert rel(gx, cx) <= 1e-5 and rel(gv, cv) <= 1e-5 and rel(gm, cm) <= 1e-4
 
 
-@pytest.mark.parametrize("n", (600_000, 1 << 20, (1 << 21) + 3))
+@pytest.mark.parametrize("n", (163840 + 3, 600_000, 1 << 20, (1 << 21) + 3))
 def test_adjoint_symmetric_large_blocks(n):
-    """Blocks of 1024 (4 waves x 4 sinks) at 600,000 (a ragged last block),
-    2^20 and 2^21 + 3, whose partials (60 and 240 GB in all) are folded in
-    bands of the default workspace: one step forward and back, against the
-    one-sided kernel with the FP64-summed policy on every particle."""
+    """Blocks of 1024 (4 waves x 4 sinks) from 163840 + 3 and at 600,000 (a
+    ragged last block), 2^20 and 2^21 + 3, whose partials (30 and 120 GB in
+    all) are folded in bands of the default workspace: one step forward and
+    back, against the one-sided kernel with the FP64-summed policy on every
+    particle."""
     S, K = 1, 1
     x, v, m, y = _problem(n, 95)
     eps, dt = 2.0 ** -10, 2.0 ** -11

@@ -1,7 +1,7 @@
 """GPU parity of the symmetric (third-law) force pass, which the library
 uses for one set acting on itself with the tile-compensated and the plain
 FP32 policies from 12288 particles on: blocks of 256 or 512 particles below
-2^17, 1024 below 2^18, 2048 from there, a work item per block pair, FP32
+81920, 1024 below 2^18, 2048 from there, a work item per block pair, FP32
 partials per block added in a fixed order.
 
 Checked against the FP64 oracle (all sinks up to 20000, sampled sinks above),
@@ -26,7 +26,7 @@ TOLS = {"f32": 1e-5, "f64": 1e-12}
 # blocks of 256 (12288 .. 24575), 512, 1024 and 2048 (eight sinks per lane,
 # from 2^18); ragged last blocks and tiles
 SYM_NS = (12288, 12289, 14000, 16384, 16385, 20000, 24576 + 7, 32768, 32769, 32768 + 255, 40000, 65535, 65536,
-          65536 + 1000, 131072 + 77, 262144 + 1, 262144 + 2047)
+          65536 + 1000, 81920 + 5, 131072 + 77, 262144 + 1, 262144 + 2047)
 
 
 def _classic(xd, md, eps):
