@@ -90,15 +90,14 @@ def executed_flop(kind, n, info, force_sums=True):
 def checkpoint_interval(arg, R, n, pos_bytes):
     """The rollout's checkpoint interval: `arg` if it is an integer, else
     (auto) the smallest K >= 1 whose R // K + 1 slots of 9 n position-type
-    values fit in a quarter of the free device memory."""
+    values fit in a quarter of the free device memory (the rule of
+    rollout(..., ckpt_every="auto"))."""
     if str(arg) != "auto":
         return max(1, int(arg))
     import torch
+    from paper_2411_18889_amd.autograd import checkpoint_interval as fit
     free, _ = torch.cuda.mem_get_info()
-    for K in range(1, max(1, R) + 1):
-        if (R // K + 1) * 9 * n * pos_bytes <= free // 4:
-            return K
-    return max(1, R)
+    return fit(R, n, pos_bytes, free // 4)
 
 
 def adjoint_schedule(R, K):

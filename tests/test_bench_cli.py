@@ -100,3 +100,17 @@ def test_traffic_summary_from_counter_folders(tmp_path):
     assert rec["write_bytes_per_pass"] == (8 * 30 + 8 * 10) * 1024 * 1.0 / 4
     assert rec["bytes_per_launch"] == rec["fetch_bytes_per_pass"] + rec["write_bytes_per_pass"]
     assert rec["source_sha256"] == bench.kernel_source_hash("adjoint_sym_kernel")
+
+
+def test_checkpoint_interval_rule():
+    """rollout(..., ckpt_every="auto") and bench.py --ckpt-every auto: the
+    smallest interval whose nsteps // K + 1 slots of 9 n values fit."""
+    from paper_2411_18889_amd.autograd import checkpoint_interval
+    n, e = 1 << 20, 8
+    slot = 9 * n * e
+    assert checkpoint_interval(10, n, e, 11 * slot) == 1       # every step fits
+    assert checkpoint_interval(10, n, e, 11 * slot - 1) == 2   # 6 slots
+    assert checkpoint_interval(10, n, e, 3 * slot) == 4        # 3 slots (10 // 4 + 1)
+    assert checkpoint_interval(10, n, e, 2 * slot) == 6        # 2 slots (10 // 6 + 1)
+    assert checkpoint_interval(10, n, e, 0) == 10              # none fits: one interval
+    assert checkpoint_interval(0, n, e, slot) == 1

@@ -125,6 +125,18 @@ def test_checkpoint_interval_invariance():
             assert rel(a, b) <= 1e-12
 
 
+def test_auto_checkpoint_interval_is_every_step_when_it_fits():
+    """ckpt_every="auto" at a size whose per-step checkpoints fit: bitwise
+    the gradients of ckpt_every=1 (symmetric passes, tile-compensated)."""
+    n, S = 20000, 4
+    x, v, m, y = _problem(n, 81)
+    eps, dt = 2.0 ** -7, 2.0 ** -8
+    a = _gpu_grads(x, v, m, y, eps, dt, S, "auto", "mix_tilec")[:3]
+    b = _gpu_grads(x, v, m, y, eps, dt, S, 1, "mix_tilec")[:3]
+    for p, q in zip(a, b):
+        assert np.array_equal(p, q)
+
+
 def test_split_calls_equal_one_call():
     """Three nbody_step_adjoint calls over consecutive spans (flags
     ENTRY_HALF / EXIT_FULL) give the same gradient as the oracle."""
