@@ -8,8 +8,10 @@
 //   (J^T lam)_k = G sum_j T(d) (m_k lam_j - m_j lam_k)      (position adjoint)
 //   (G^T lam)_k = -G sum_j (lam_j . d) s^-3/2               (mass adjoint)
 // The j = k term is zero in all three (d = 0 and m_k lam_k - m_k lam_k = 0).
-// The first is needed anyway to walk the state back one step, so it comes
-// almost free: it shares d, s and the reciprocal square root.
+// The first is needed to walk the state back one step and comes almost
+// free: it shares d, s and the reciprocal square root. A pass that does not
+// walk the state back (the entry pass, a state reloaded from a checkpoint)
+// leaves it out: 6 % (FP64) to 20 % (mixed, FP64 sums) faster at 262144.
 //
 // Per pair, with u = m_k lam_j - m_j lam_k and e = -3 s^-1 (d . u):
 //   T(d) u = s^-3/2 (u + e d)
@@ -89,7 +91,9 @@ __device__ __forceinline__ void finish_adj(const AdjArgs<Pol>& a, int i, const d
     }
 }
 
-template <class Pol, int BS, int K>
+// F: also sum the force a (quantities 0..2, for a pass that walks the state
+// back); without it they stay 0 and the pair body is 4 operations shorter.
+template <class Pol, int BS, int K, bool F>
 __global__ __launch_bounds__(BS) void adjoint_kernel(AdjArgs<Pol> a) {
     using calc_t = typename Pol::calc_t;
     using sum_t = typename Pol::sum_t;
@@ -167,11 +171,12 @@ __global__ __launch_bounds__(BS) void adjoint_kernel(AdjArgs<Pol> a) {
                 const calc_t r = rsqrt_pair(ss);
                 const calc_t r2 = r * r;
                 const calc_t r3 = r2 * r;
-                // force
-                const calc_t w = r3 * q.w;
-                s[k][0].add_fma(dx, w);
-                s[k][1].add_fma(dy, w);
-                s[k][2].add_fma(dz, w);
+                if (F) {  // force
+                    const calc_t w = r3 * q.w;
+                    s[k][0].add_fma(dx, w);
+                    s[k][1].add_fma(dy, w);
+                    s[k][2].add_fma(dz, w);
+                }
                 // position adjoint: T(d) u = r3 (u + e d), e = -3 r2 (d . u)
                 const calc_t ux = fmat(mi[k], lj.x, -(q.w * lxi[k]));
                 const calc_t uy = fmat(mi[k], lj.y, -(q.w * lyi[k]));
@@ -233,7 +238,10 @@ int split_span(int64_t n, int split, int block) {
 template <class Pol, int BS, int K>
 hipError_t launch_shape(AdjArgs<Pol> a, int nsplit, hipStream_t stream) {
     dim3 grid((a.n + BS * K - 1) / (BS * K), nsplit);
-    hipLaunchKernelGGL((adjoint_kernel<Pol, BS, K>), grid, dim3(BS), 0, stream, a);
+    if (a.update_state)
+        hipLaunchKernelGGL((adjoint_kernel<Pol, BS, K, true>), grid, dim3(BS), 0, stream, a);
+    else
+        hipLaunchKernelGGL((adjoint_kernel<Pol, BS, K, false>), grid, dim3(BS), 0, stream, a);
     return hipGetLastError();
 }
 
