@@ -205,3 +205,26 @@ def test_max_size_source_set():
     e, ep = rel(ah, ref), rel(ph, rpot)
     print("16 sinks x 2^30 sources: e_glob %.3g, potential %.3g" % (e, ep))
     assert e <= TOL[prec] and ep <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["mix_tilec", "f32", "f64"])
+def test_one_shard_of_eight(prec):
+    """One GPU's share of the scale-2^20 force pass sharded by sinks over
+    eight GPUs: the last N/8 particles as sinks against all N as sources
+    (separate sets, the one-sided kernel). 512 seeded sinks of the shard
+    against the oracle, and the whole shard against the same rows of the
+    pass of the set on itself (the symmetric kernel: another order of the
+    same sums)."""
+    x, v, m = make_state("scale-2^20")
+    n = x.shape[1]
+    ni = n // 8
+    eps = 2.0 ** -10
+    xd, _, md = to_dev(x, v, m, prec)
+    xi = xd[:, n - ni:].contiguous()
+    a = host(nb.accel(xi, md, eps, prec=prec, xj=xd))
+    full = host(nb.accel(xd, md, eps, prec=prec))[:, n - ni:]
+    idx = np.sort(np.random.default_rng(31).choice(ni, 512, replace=False))
+    ref = oracle.accel_sampled(host(xd), host(md), eps, idx + (n - ni))
+    e, e_full = rel(a[:, idx], ref), rel(a, full)
+    print("%s: shard %d x %d sampled e_glob %.3g, against the full pass %.3g" % (prec, ni, n, e, e_full))
+    assert e <= TOL[prec] and e_full <= TOL[prec]

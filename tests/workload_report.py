@@ -3,7 +3,8 @@ the FP64 oracle, energy drift, the adjoint's cost and gradient error, pass
 times across N and the oracle's own CPU rate -- every figure of the result
 tables, regenerated from committed code on one GPU.
 
-    python tests/workload_report.py [--only NAME ...] [--skip-scan] [--skip-cpu]
+    python tests/workload_report.py [--only NAME ...] [--skip-scan] [--skip-shard]
+                                    [--skip-cpu]
 
 Prints markdown on stdout (progress on stderr). Test infrastructure: it uses
 the oracle (oracle/) for the reference values, as the GPU tests do.
@@ -251,6 +252,44 @@ def pass_scan():
     return out
 
 
+def shard_rows(G=8):
+    """One GPU's share of the scale-2^20 force pass sharded by sinks over G
+    GPUs: `nbody_accel` of the first N/G particles against all N (the
+    one-sided kernel, separate sink and source sets), beside the full
+    symmetric pass of the set on itself; sampled error of the shard against
+    the oracle (256 seeded sinks)."""
+    import torch
+    import paper_2411_18889_amd as nb
+    from tests.gpu_util import host, to_dev
+    w = WORKLOADS["scale-2^20"]
+    x, v, m = make_state("scale-2^20")
+    n = x.shape[1]
+    ni = n // G
+    out = []
+    for prec in ("mix_tilec", "f32", "f64"):
+        log("shard %s" % prec)
+        xd, _, md = to_dev(x, v, m, prec)
+        xi = xd[:, :ni].contiguous()
+        ai = torch.empty_like(xi)
+        L = nb._lib.lib()
+        wsi = torch.empty(max(1, int(L.nbody_pass_workspace_size(0, ni, n, nb._lib.PREC[prec], 0, 0,
+                                                                     None))),
+                          dtype=torch.uint8, device="cuda")
+        ws = torch.empty(max(1, nb.workspace_size(0, n, prec)), dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: nb.accel(xi, md, w.eps, prec=prec, xj=xd, out=ai, workspace=wsi))
+        full = timed(lambda: nb.accel(xd, md, w.eps, prec=prec, workspace=ws), reps=3)
+        a = host(nb.accel(xi, md, w.eps, prec=prec, xj=xd))
+        idx = np.sort(np.random.default_rng(11).choice(ni, 256, replace=False))
+        xs = host(xd)
+        ref = oracle.accel_sampled(xs, host(md), w.eps, idx)
+        e = float(np.linalg.norm(a[:, idx] - ref) / np.linalg.norm(ref))
+        peak = FP64_PEAK if prec == "f64" else FP32_PEAK
+        out.append({"prec": prec, "ni": ni, "n": n, "ms": ms, "full": full,
+                    "gint": ni * float(n) / ms / 1e6,
+                    "frac": 20.0 * ni * float(n) / (ms * 1e-3) / peak, "e": e})
+    return out
+
+
 def cpu_table():
     out = []
     k0 = oracle.num_threads()
@@ -274,6 +313,7 @@ def main():
     ap.add_argument("--only", nargs="*", default=list(WORKLOADS))
     ap.add_argument("--skip-scan", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-shard", action="store_true")
     args = ap.parse_args()
     import paper_2411_18889_amd as nb
     print("Device: %s. Command: `python tests/workload_report.py%s`\n"
@@ -328,6 +368,20 @@ def main():
             print("| %d | %s | %s | %s | %s | %s | %s | %s |" % (
                 r["n"], cell("force_mix_tilec"), cell("pot"), cell("adj_mix_tilec"), cell("adj0"),
                 cell("force_f32"), cell("force_f64"), cell("adj_f64")))
+        print(clock_line(clk))
+    if not args.skip_shard:
+        print("\nOne GPU's share of the scale-2^20 force pass sharded by sinks over 8 GPUs "
+              "(`nbody_accel` of N/8 sinks against all N sources, one-sided kernel; best of 5) "
+              "beside the full symmetric pass on one GPU (best of 3)\n")
+        print("| precision | sinks x sources | shard pass | Ginteractions/s | % peak (20-flop) "
+              "| full pass, one GPU | full / 8 | e_glob (256 sinks) |")
+        print("|---|---|---:|---:|---:|---:|---:|---:|")
+        with bench.ClockSampler() as clk:
+            shards = shard_rows()
+        for r in shards:
+            print("| %s | %d x %d | %.4g ms | %.0f | %.1f %% | %.4g ms | %.4g ms | %.2g |" % (
+                r["prec"], r["ni"], r["n"], r["ms"], r["gint"], 100 * r["frac"], r["full"],
+                r["full"] / 8, r["e"]))
         print(clock_line(clk))
     if not args.skip_cpu:
         rows, k0 = cpu_table()
