@@ -208,6 +208,20 @@ class ClockSampler:
                 "samples": len(v), "source": "sysfs pp_dpm_sclk, every %.1f s" % self.period}
 
 
+# the clock-scaled fractions need the clock under load: at least this many
+# samples (half a second of timed work at the default period); a short timed
+# region may catch only the ramp from idle
+MIN_CLOCK_SAMPLES = 5
+
+
+def frac_at_clock(frac, clk):
+    """`frac` against the peak scaled to the mean measured shader clock, or
+    None when the sampler has too few samples for a clock under load."""
+    if not clk or clk.get("samples", 0) < MIN_CLOCK_SAMPLES:
+        return None
+    return frac * PEAK_CLOCK_MHZ / clk["sclk_mhz_mean"]
+
+
 def kernel_source_hash(kernel):
     import hashlib
     h = hashlib.sha256()
@@ -582,10 +596,14 @@ def main():
     roof = roof_adj if dom == "adjoint" else force_roof
 
     clk = clocks.summary()
-    if clk:
+    for r in (roof_adj, force_roof):
         # the same achieved rate against the peak scaled to the measured clock
-        for r in (roof_adj, force_roof):
-            r["frac_at_measured_sclk"] = r["frac"] * PEAK_CLOCK_MHZ / clk["sclk_mhz_mean"]
+        f = frac_at_clock(r["frac"], clk)
+        if f is not None:
+            r["frac_at_measured_sclk"] = f
+    if clk and clk["samples"] < MIN_CLOCK_SAMPLES:
+        clk["note"] = ("fewer than %d samples: too short a timed region for the clock under load"
+                       % MIN_CLOCK_SAMPLES)
 
     D0 = nb.diag_dict(d0)
     D1 = nb.diag_dict(d1)

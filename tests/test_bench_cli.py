@@ -29,6 +29,11 @@ def test_clock_sampler_stops_and_summarises():
         assert s["samples"] >= 1
     c.samples = [2000.0, 2400.0]
     assert c.summary()["sclk_mhz_mean"] == 2200.0
+    # two samples are too few for a clock-scaled fraction; five are enough
+    assert bench.frac_at_clock(0.5, c.summary()) is None
+    c.samples = [2000.0] * 5
+    assert bench.frac_at_clock(0.5, c.summary()) == 0.5 * 2400 / 2000
+    assert bench.frac_at_clock(0.5, {}) is None
 
 
 def test_tuner_cli_help():
