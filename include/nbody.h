@@ -32,13 +32,11 @@
  *   (nbody_pass_info reports which): a one-sided kernel (every sink sums all
  *   sources; optional split of the source range with FP64 partials), or, for
  *   NB_MIX_TILEC, NB_F32 and NB_F64 with one set acting on itself from 12288
- *   particles (the adjoint: NB_MIX_TILEC only), a
- *   symmetric pass that evaluates each pair once for both bodies (Newton's
- *   third law) and adds partials per particle block (FP32; FP64 for NB_F64)
- *   in block order. No
- *   atomics in either: the same call on the same inputs gives bitwise the
- *   same results. Results of different forms or launch shapes differ by
- *   rounding only.
+ *   particles (force and adjoint), a symmetric pass that evaluates each pair
+ *   once for both bodies (Newton's third law) and adds partials per particle
+ *   block (FP32; FP64 for NB_F64) in block order. No atomics in either: the
+ *   same call on the same inputs gives bitwise the same results. Results of
+ *   different forms or launch shapes differ by rounding only.
  *
  * Streams and synchronisation
  *   `stream` is a hipStream_t (NULL = the default stream). Every entry point
@@ -142,14 +140,15 @@ typedef enum nb_op {
  *     split       j-split: number of source ranges per sink, 1..256; partial
  *                 sums are combined in a fixed order
  *   symmetric = 1: the symmetric (third-law) pass of one set on itself
- *                 (force: NB_MIX_TILEC, NB_F32, NB_F64; adjoint: NB_MIX_TILEC)
+ *                 (NB_MIX_TILEC, NB_F32, NB_F64)
  *     block       threads per workgroup, waves x 64; with i_per_lane sinks
  *                 per lane, blocks of block x i_per_lane particles. Shapes
  *                 (block, i_per_lane): force (128, 2), (256, 2), (512, 2),
  *                 (1024, 2), (128, 4), (256, 4), (512, 4), (1024, 4), (128, 8),
  *                 (256, 8), (512, 8);
- *                 adjoint (128, 2), (256, 2), (512, 2), (1024, 2), (256, 1),
- *                 (512, 1), (128, 4), (256, 4), (512, 4) (with eight sinks per
+ *                 adjoint (128, 2), (256, 2), (512, 2), (1024, 2) (not
+ *                 NB_F64), (256, 1), (512, 1), (128, 4), (256, 4), (512, 4)
+ *                 (with eight sinks per
  *                 lane for the force, and four for the adjoint, each sink's
  *                 sum in NB_MIX_TILEC is an FP32 running sum over the source
  *                 block, as the source side's always is)
@@ -379,10 +378,10 @@ size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int s
  * symmetric = 1: the third-law pass -- particles cut into blocks of
  * block_particles = block * i_per_lane, one workgroup per block pair,
  * partials per block (FP32; FP64 for NB_F64) added in a fixed order
- * (NB_MIX_TILEC, and NB_F32 and NB_F64 for the force, from 12288 up to
- * 2^28 particles; from 2^18 the force takes blocks of 2048 particles and
- * the adjoint blocks of 1024 at every n; the partials are written and
- * folded in bands of the workspace).
+ * (NB_MIX_TILEC, NB_F32 and NB_F64, from 12288 up to 2^28 particles; from
+ * 2^18 the force takes blocks of 2048 particles and the adjoint blocks of
+ * 1024 at every n; the partials are written and folded in bands of the
+ * workspace).
  * symmetric = 0: the one-sided kernel in the shape (i_per_lane, block,
  * split).
  */

@@ -452,15 +452,15 @@ hipError_t launch_adjoint(int prec, const Shape& shape, int64_t n, const void* x
                           void* drift_x = nullptr, double drift_dt = 0.0,
                           bool* drifted = nullptr);
 
-// Symmetric form of the fused adjoint pass (NB_MIX_TILEC only), same
-// contract as launch_adjoint; ws holds ws_bytes >= sym_min_bytes(
-// adjoint_sym_layout(sh, n, true)) bytes, used in bands as the force pass.
-// force_sums: the layout of a pass that also sums a(x) (seven quantities;
-// four without), which update_state asks for.
+// Symmetric form of the fused adjoint pass (NB_MIX_TILEC, NB_F32, NB_F64),
+// same contract as launch_adjoint; ws holds ws_bytes >= sym_min_bytes(
+// adjoint_sym_layout(prec, sh, n, true)) bytes, used in bands as the force
+// pass. force_sums: the layout of a pass that also sums a(x) (seven
+// quantities; four without), which update_state asks for.
 SymShape choose_adjoint_sym_shape(int prec, int64_t n);
 bool adjoint_sym_shape_supported(int prec, const SymShape& s);
-SymLayout adjoint_sym_layout(const SymShape& s, int64_t n, bool force_sums);
-hipError_t launch_adjoint_sym(const SymShape& sh, int64_t n, const void* x, const void* m,
+SymLayout adjoint_sym_layout(int prec, const SymShape& s, int64_t n, bool force_sums);
+hipError_t launch_adjoint_sym(int prec, const SymShape& sh, int64_t n, const void* x, const void* m,
                               const void* lam_v, double eps, double G, double c,
                               bool update_state, double h, void* acc, void* v, void* lam_x,
                               double* lam_m, void* ws, size_t ws_bytes, hipStream_t stream,

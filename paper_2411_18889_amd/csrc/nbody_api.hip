@@ -265,9 +265,9 @@ int resolve_adjoint(int prec, int64_t n, const nb_launch* launch, SymShape* sym,
     return adjoint_shape_supported(*sh) ? NB_OK : NB_EUNSUPPORTED;
 }
 
-size_t adjoint_partials_need(const SymShape& sym, const Shape& sh, int64_t n, bool least) {
+size_t adjoint_partials_need(int prec, const SymShape& sym, const Shape& sh, int64_t n, bool least) {
     if (sym.waves) {
-        const SymLayout L = adjoint_sym_layout(sym, n, true);
+        const SymLayout L = adjoint_sym_layout(prec, sym, n, true);
         return least ? sym_min_bytes(L) : sym_default_bytes(L);
     }
     return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
@@ -538,10 +538,10 @@ int adjoint_common(int64_t n, void* x, void* v, const void* m, void* acc, void* 
     SymShape sym;
     int st = resolve_adjoint(prec, n, launch, &sym, &sh);
     if (st != NB_OK) return st;
-    const size_t need = adjoint_partials_need(sym, sh, n, true);
+    const size_t need = adjoint_partials_need(prec, sym, sh, n, true);
     st = check_ws(ws, ws_bytes, need);
     if (st != NB_OK) return st;
-    const size_t used = sym.waves ? std::min(ws_bytes, sym_full_bytes(adjoint_sym_layout(sym, n, true)))
+    const size_t used = sym.waves ? std::min(ws_bytes, sym_full_bytes(adjoint_sym_layout(prec, sym, n, true)))
                                   : need;
     if (used) {
         if (overlaps(ws, used, m, (size_t)n * ms)) return NB_EINVAL;
@@ -565,7 +565,7 @@ int adjoint_common(int64_t n, void* x, void* v, const void* m, void* acc, void* 
         return timed(NB_PROF_ADJOINT, s, [&] {
             void* dx = drift ? x : nullptr;
             if (sym.waves)
-                return launch_adjoint_sym(sym, n, x, m, lam_v, eps, G, c, update_state, h, acc, v,
+                return launch_adjoint_sym(prec, sym, n, x, m, lam_v, eps, G, c, update_state, h, acc, v,
                                           lam_x, lm, ws, used, s, dx, dt, &drifted);
             return launch_adjoint(prec, sh, n, x, m, lam_v, eps, G, c, update_state, h, acc, v, lam_x,
                                   lm, ws, s, dx, dt, &drifted);
@@ -668,7 +668,7 @@ size_t nbody_pass_workspace_size(int op, int64_t ni, int64_t nj, int prec, int s
     Shape sh;
     if (op == NB_OP_ADJOINT) {
         if (ni != nj || resolve_adjoint(prec, ni, launch, &sym, &sh) != NB_OK) return 0;
-        return adjoint_partials_need(sym, sh, ni, false);
+        return adjoint_partials_need(prec, sym, sh, ni, false);
     }
     if (op != NB_OP_ACCEL || (self_set && ni != nj)) return 0;
     if (resolve_accel(prec, ni, nj, self_set != 0, potential != 0, launch, &sym, &sh) != NB_OK)
@@ -694,7 +694,7 @@ size_t nbody_workspace_size(int op, int64_t n, int prec) {
     }
     case NB_OP_ADJOINT: {
         const SymShape sym = choose_adjoint_sym_shape(prec, n);
-        if (sym.waves) return sym_default_bytes(adjoint_sym_layout(sym, n, true));
+        if (sym.waves) return sym_default_bytes(adjoint_sym_layout(prec, sym, n, true));
         const Shape sh = choose_adjoint_shape(prec, n);
         return sh.split > 1 ? adjoint_partials_bytes(sh, n) : 0;
     }

@@ -35,6 +35,7 @@ import os
 import sys
 
 # shapes the library is built for (nb_launch in include/nbody.h)
+SYM_PRECS = ("mix_tilec", "f32", "f64")  # the policies with symmetric passes
 SYM_FORCE = [(2, 128), (2, 256), (2, 512), (2, 1024), (4, 128), (4, 256), (4, 512), (4, 1024),
              (8, 128), (8, 256), (8, 512)]
 SYM_ADJOINT = [(2, 128), (2, 256), (2, 512), (2, 1024), (1, 256), (1, 512), (4, 128), (4, 256),
@@ -87,6 +88,8 @@ def candidate_shapes(op, n, prec, sym_pass):
         shapes.append({"i_per_lane": ipl, "block": block, "split": split, "symmetric": 0})
     if sym_pass:
         for ipl, block in (SYM_FORCE if op == "force" else SYM_ADJOINT):
+            if op != "force" and prec == "f64" and block > 512:
+                continue  # the FP64 adjoint: up to 8 waves (16 would spill)
             if block * ipl <= n:
                 shapes.append({"i_per_lane": ipl, "block": block, "split": 0, "symmetric": 1})
     return shapes
@@ -115,7 +118,7 @@ def tune(n, prec, op="force", eps=2.0 ** -8, shapes=None, reps=None, seed=5, one
     X = torch.tensor(x, dtype=pdt, device=dev)
     V = torch.tensor(v, dtype=pdt, device=dev)
     M = torch.tensor(m, dtype=api.mass_dtype(prec), device=dev)
-    sym_pass = bool(api.pass_info(1 if op == "force" else 2, max(n, 12288), prec)["symmetric"])
+    sym_pass = prec in SYM_PRECS
     if reps is None:
         reps = max(2, min(200, int(2e11 // (n * n))))
     if shapes is None:
@@ -155,8 +158,9 @@ def tune(n, prec, op="force", eps=2.0 ** -8, shapes=None, reps=None, seed=5, one
 
     # shapes differ by the rounding of the FP32 pair arithmetic: within the
     # accuracy bars of the results (1e-5 for accelerations; 1e-4 for the
-    # gradient terms, whose pair sums cancel more)
-    tol = 1e-12 if prec == "f64" else (1e-5 if op == "force" else 1e-4)
+    # gradient terms, whose pair sums cancel more; 1e-3 for them with plain
+    # FP32 running sums, whose order differs most between shapes)
+    tol = 1e-12 if prec == "f64" else (1e-5 if op == "force" else (1e-3 if prec == "f32" else 1e-4))
     base = compare(None)
     lib_call = lambda: run(None)
     _warm_up(lib_call, reset=reset)

@@ -112,8 +112,19 @@ def test_workspace_size(L):
         assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + G4, n
     n = 1 << 28
     assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + 7 * 4 * (n + 262143 * 1024)
-    # the one-sided adjoint kernel (other policies): split partials or none
-    assert L.nbody_workspace_size(2, 1 << 20, F64) == 8 * 7 * (1 << 20) * 8
+    # FP32 and FP64 take the symmetric adjoint too (FP64: FP64 partials, in
+    # blocks of 256 below 32768, 512 below 163840, 1024 from there; FP32 as
+    # the tile-compensated policy); the running sums are FP64 for all three
+    assert L.nbody_workspace_size(2, 16384, F64) == 64 * 7 * 16384 * 8
+    assert L.nbody_workspace_size(2, 1 << 17, F64) == 256 * 7 * (1 << 17) * 8
+    assert L.nbody_workspace_size(2, 1 << 18, F64) == 256 * 7 * (1 << 18) * 8
+    assert L.nbody_workspace_size(2, 1 << 20, F64) == 7 * (1 << 20) * 8 + G4
+    assert L.nbody_workspace_size(2, 65536, F32) == 128 * 7 * 65536 * 4
+    assert L.nbody_workspace_size(2, 1 << 20, F32) == 7 * (1 << 20) * 8 + G4
+    # the one-sided adjoint kernel (other policies, and below 12288):
+    # split partials or none
+    assert L.nbody_workspace_size(2, 1 << 20, 3) == 8 * 7 * (1 << 20) * 8
+    assert L.nbody_workspace_size(2, 8192, F64) == 32 * 7 * 8192 * 8
 
 
 def _skip_if_device(L):
@@ -301,12 +312,20 @@ def test_pass_info(L):
         assert (info.symmetric, info.block_particles) == (1, b)
     assert L.nbody_pass_info(1, (1 << 28) + 1, TILEC, ctypes.byref(info)) == 0
     assert info.symmetric == 0
-    assert L.nbody_pass_info(2, 1 << 20, F64, ctypes.byref(info)) == 0 and info.symmetric == 0
+    # the FP64 and FP32 adjoint: symmetric too (FP64 with four sinks per
+    # lane from 32768); the compensated policies keep the one-sided kernel
+    assert L.nbody_pass_info(2, 1 << 20, F64, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
+    assert L.nbody_pass_info(2, 65536, F64, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 128, 4, 512)
+    assert L.nbody_pass_info(2, 1 << 20, F32, ctypes.byref(info)) == 0
+    assert (info.symmetric, info.block_particles) == (1, 1024)
+    assert L.nbody_pass_info(2, 1 << 20, 3, ctypes.byref(info)) == 0 and info.symmetric == 0
     assert L.nbody_pass_info(1, 1000, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
     # the symmetric passes start at 12288 particles
-    for op in (1, 2):
-        assert L.nbody_pass_info(op, 12287, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 0
-        assert L.nbody_pass_info(op, 12288, TILEC, ctypes.byref(info)) == 0 and info.symmetric == 1
+    for op, prec in ((1, TILEC), (2, TILEC), (2, F64), (2, F32)):
+        assert L.nbody_pass_info(op, 12287, prec, ctypes.byref(info)) == 0 and info.symmetric == 0
+        assert L.nbody_pass_info(op, 12288, prec, ctypes.byref(info)) == 0 and info.symmetric == 1
         assert info.block_particles == 256
     assert L.nbody_pass_info(0, 1000, TILEC, ctypes.byref(info)) == NB_EINVAL
     assert L.nbody_pass_info(1, 0, TILEC, ctypes.byref(info)) == NB_EINVAL
@@ -402,7 +421,8 @@ def test_explicit_pass_shapes_validated(L):
         lx, lv, lm, v = P(320 * MiB), P(384 * MiB), P(448 * MiB), P(512 * MiB)
         return L.nbody_step_adjoint_ex(n, x, v, m, acc, lx, lv, lm, 0.01, 1.0, 0.01, 1, prec, 0,
                                        None, 0, 0, ctypes.byref(ln), None, 0, None)
-    assert adj((2, 256, 0, 1), prec=F64) == NB_EUNSUPPORTED       # FP64: one-sided only
+    assert adj((2, 256, 0, 1), prec=3) == NB_EUNSUPPORTED         # Kahan: one-sided only
+    assert adj((2, 1024, 0, 1), prec=F64) == NB_EUNSUPPORTED      # FP64: up to 8 waves
     assert adj((3, 256, 0, 1)) == NB_EUNSUPPORTED                 # adjoint: 1, 2 or 4 per lane
     assert adj((4, 1024, 0, 1)) == NB_EUNSUPPORTED                # 4 per lane: up to 8 waves
     assert adj((1, 128, 0, 1)) == NB_EUNSUPPORTED                 # 1 per lane: 4 or 8 waves
@@ -418,6 +438,8 @@ def test_explicit_pass_shapes_validated(L):
     assert q(0, 20000, 20000, F64, 1, 0, ctypes.byref(ln)) == 40 * 3 * 20000 * 8
     assert q(0, 20000, 20000, TILEC, 0, 0, ctypes.byref(ln)) == 0  # separate sets: refused
     assert q(2, 20000, 20000, TILEC, 1, 0, ctypes.byref(ln)) == 40 * 7 * 20000 * 4
+    assert q(2, 20000, 20000, F32, 1, 0, ctypes.byref(ln)) == 40 * 7 * 20000 * 4
+    assert q(2, 20000, 20000, F64, 1, 0, ctypes.byref(ln)) == 40 * 7 * 20000 * 8
     ln = nb_launch(1, 256, 5, 0)
     assert q(2, 20000, 20000, F64, 1, 0, ctypes.byref(ln)) == 5 * 7 * 20000 * 8
     assert q(0, 20000, 700, TILEC, 0, 0, ctypes.byref(ln)) == 5 * 4 * 20000 * 8

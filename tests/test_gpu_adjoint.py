@@ -41,8 +41,11 @@ def _gpu_grads(x, v, m, y, eps, dt, S, K, prec):
     return host(xd.grad), host(vd.grad), host(md.grad), (host(xd), host(vd), host(md))
 
 
-@pytest.mark.parametrize("n,S,K", [(64, 6, 2), (300, 12, 5), (1000, 9, 20)])
+@pytest.mark.parametrize("n,S,K", [(64, 6, 2), (300, 12, 5), (1000, 9, 20), (12288 + 5, 3, 2),
+                                   (40000 + 77, 2, 1)])
 def test_adjoint_f64_matches_oracle(n, S, K):
+    """Up to 1000 particles the one-sided kernel; from 12288 the symmetric
+    pass (FP64 partials; 40077: four sinks per lane, blocks of 512)."""
     x, v, m, y = _problem(n, 60 + n)
     eps, dt = 2.0 ** -5, 2.0 ** -7
     gx, gv, gm, _ = _gpu_grads(x, v, m, y, eps, dt, S, K, "f64")
@@ -221,44 +224,88 @@ def test_adjoint_symmetric_checkpoint_interval_invariance():
             assert rel(a, b) <= 1e-7
 
 
+@pytest.mark.parametrize("prec", ("mix_tilec", "f64", "f32"))
 @pytest.mark.parametrize("walk", (False, True))
-def test_adjoint_pass_full_size_against_oracle_rows(walk):
-    """scale-2^20, in the launch configuration the benchmark times: one fused
+def test_adjoint_pass_full_size_against_oracle_rows(walk, prec):
+    """scale-2^20, in the launch configuration the benchmark times (and the
+    FP64 and FP32 policies' symmetric passes at the same size): one fused
     adjoint pass against the oracle's transposed Jacobians on sampled rows.
     walk = False: the entry pass (state from the caller, force sums skipped);
     walk = True: one step walked back with a tiny dt, so the pass also
-    computes a(x) and steps the velocity (the force-summing kernel)."""
+    computes a(x) and steps the velocity (the force-summing kernel); the
+    oracle then takes the walked-back state the call leaves."""
     from nbody_inputs import make_state
     from tests.gpu_util import sample_indices
     x, v, m = make_state("scale-2^20")
     n = x.shape[1]
     eps, G = 2.0 ** -10, 1.0
-    xd, vd, md = to_dev(x, v, m, "mix_tilec")
-    assert nb.pass_info(2, n, "mix_tilec")["symmetric"] == 1
-    acc = nb.accel(xd, md, eps, prec="mix_tilec")
-    lam = torch.tensor(np.random.default_rng(11).normal(size=(3, n)), device=DEV)
+    xd, vd, md = to_dev(x, v, m, prec)
+    assert nb.pass_info(2, n, prec)["symmetric"] == 1
+    acc = nb.accel(xd, md, eps, prec=prec)
+    lam = torch.tensor(np.random.default_rng(11).normal(size=(3, n)), dtype=nb.pos_dtype(prec),
+                       device=DEV)
     lx = torch.zeros_like(lam)
     lm = torch.zeros(n, dtype=torch.float64, device=DEV)
     if walk:
         dt = 2.0 ** -24
         h = 0.5 * dt
-        # the state the pass will see: the reverse drift's arithmetic, in FP64
-        vh = host(vd) - h * host(acc)
-        xw = host(xd) - dt * vh
-        nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 1, G=G, prec="mix_tilec")
+        nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 1, G=G, prec=prec)
         c = h  # the last (and only) pass of a walk ending at step 0
     else:
         dt = 2.0 ** -11
-        xw = host(xd)
-        nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 0, G=G, prec="mix_tilec",
+        nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 0, G=G, prec=prec,
                         entry_half=True)
         c = 0.5 * dt
+    xw = host(xd)  # the state the pass saw
     idx = sample_indices(xw, 256, 32, seed=12)
     jt, gt = oracle.vjp_sampled(xw, host(md), host(lam), eps, idx, G=G)
     ex = rel(host(lx)[:, idx] / c, jt)
     em = rel(host(lm)[idx] / c, gt)
-    print("scale-2^20 adjoint pass (walk=%s): J^T lam rel err %.3g, G^T lam %.3g" % (walk, ex, em))
-    assert ex <= 1e-4 and em <= 1e-4
+    print("scale-2^20 %s adjoint pass (walk=%s): J^T lam rel err %.3g, G^T lam %.3g"
+          % (prec, walk, ex, em))
+    tol = 1e-12 if prec == "f64" else 1e-4
+    assert ex <= tol and em <= tol
     if walk:  # the pass also left a(x) of the walked-back state
         ea = rel(host(acc)[:, idx], oracle.accel_sampled(xw, host(md), eps, idx))
-        assert ea <= 1e-5
+        assert ea <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("ipl,block", [(2, 128), (2, 256), (2, 512), (1, 256), (4, 128), (4, 256)])
+@pytest.mark.parametrize("prec", ("f64", "f32"))
+def test_adjoint_symmetric_pass_fp64_fp32(prec, ipl, block):
+    """The symmetric adjoint pass in the FP64 and plain FP32 policies, in
+    explicit shapes (20037 particles: ragged last blocks): the entry pass
+    against the oracle's transposed Jacobians and against the one-sided
+    kernel, then one walked-back step (a pass with the force sums) against
+    the oracle's a(x) of the walked-back state."""
+    n, eps, dt = 20000 + 37, 2.0 ** -8, 2.0 ** -9
+    x, v, m = plummer_sphere(n, 903)
+    xd, vd, md = to_dev(x, v, m, prec)
+    pdt = nb.pos_dtype(prec)
+    lam = torch.tensor(np.random.default_rng(904).normal(size=(3, n)), dtype=pdt, device=DEV)
+    acc = nb.accel(xd, md, eps, prec=prec)
+    sym = {"i_per_lane": ipl, "block": block, "split": 0, "symmetric": 1}
+    one = {"i_per_lane": 1, "block": 256, "split": 8, "symmetric": 0}
+    out = []
+    for launch in (sym, one):
+        lx = torch.zeros_like(lam)
+        lm = torch.zeros(n, dtype=torch.float64, device=DEV)
+        nb.step_adjoint(xd, vd, md, acc, lx, lam.clone(), lm, eps, dt, 0, prec=prec,
+                        entry_half=True, launch=launch)
+        out.append((host(lx), host(lm)))
+    jt, gt = oracle.vjp(host(xd), host(md), host(lam), eps)
+    c = 0.5 * dt
+    (sx, sm), (ox, om) = out
+    errs = (rel(sx / c, jt), rel(sm / c, gt), rel(ox / c, jt), rel(om / c, gt))
+    print("%s %dx%d: symmetric J^T lam %.3g, G^T lam %.3g; one-sided %.3g, %.3g"
+          % ((prec, ipl, block) + errs))
+    tol = 1e-12 if prec == "f64" else 1e-4
+    assert max(errs[:2]) <= tol
+    if prec == "f64":
+        assert rel(sx, ox) <= 1e-13 and rel(sm, om) <= 1e-13
+    h = 0.5 * dt
+    xw = host(xd) - dt * (host(vd) - h * host(acc))
+    nb.step_adjoint(xd, vd, md, acc, torch.zeros_like(lam), lam.clone(),
+                    torch.zeros(n, dtype=torch.float64, device=DEV), eps, dt, 1, prec=prec,
+                    launch=sym)
+    assert rel(host(acc), oracle.accel(xw, host(md), eps)) <= (1e-12 if prec == "f64" else 1e-5)

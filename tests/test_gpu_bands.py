@@ -36,7 +36,7 @@ def _sizes(n, prec, op, nq):
     b = info["block_particles"]
     nblk = -(-n // b)
     elem = 8 if prec == "f64" else 4
-    fin = 4 if prec == "f32" else 8
+    fin = 4 if (prec == "f32" and op != 2) else 8  # the adjoint folds in FP64
     full = nblk * nq * n * elem
     least = _align(nq * n * fin) + nq * elem * (n + (nblk - 1) * min(n, b))
     return full, min(full, least)
@@ -95,12 +95,14 @@ def test_step_bands_bitwise(prec):
     assert rel(host(out[0][2]), ao) <= (1e-12 if prec == "f64" else 1e-5)
 
 
-@pytest.mark.parametrize("n", (40000 + 77, 262144 + 77))
-def test_adjoint_bands_bitwise(n):
+@pytest.mark.parametrize("prec,n", (("mix_tilec", 40000 + 77), ("mix_tilec", 262144 + 77),
+                                    ("f64", 40000 + 77), ("f32", 40000 + 77)))
+def test_adjoint_bands_bitwise(prec, n):
     """A three-step reverse walk (entry pass without the force sums, walked-
     back passes with them, reverse drifts fused into the folds), with two
-    sinks per lane (40077) and four (262221, blocks of 1024)."""
-    prec, S = "mix_tilec", 3
+    sinks per lane (40077) and four (262221, blocks of 1024; FP64 at 40077,
+    blocks of 512)."""
+    S = 3
     x, v, m = plummer_sphere(n, 744)
     eps, dt = 2.0 ** -8, 2.0 ** -9
     lam = np.random.default_rng(5).normal(size=(3, n))
@@ -110,7 +112,7 @@ def test_adjoint_bands_bitwise(n):
         xd, vd, md = to_dev(x, v, m, prec)
         acc = torch.empty_like(xd)
         nb.step(xd, vd, md, acc, eps, dt, S, prec=prec)
-        lx = torch.tensor(lam, device=DEV)
+        lx = torch.tensor(lam, dtype=nb.pos_dtype(prec), device=DEV)
         lv = torch.zeros_like(lx)
         lm = torch.zeros(n, dtype=torch.float64, device=DEV)
         nb.step_adjoint(xd, vd, md, acc, lx, lv, lm, eps, dt, S, prec=prec, entry_half=True,
