@@ -18,7 +18,9 @@ For every (N, precision) it times each shape on a seeded Plummer sphere with
 the workspace the library asks for that shape, checks that each shape
 returns the same result as the library's own choice (shapes differ by
 rounding only: to 1e-5 relative for the force, 1e-4 for the adjoint's
-position adjoint, 1e-12 in FP64), and reports the fastest.
+position adjoint, 1e-3 for it in the plain FP32 policy, 1e-12 in FP64),
+and reports the fastest. The symmetric family is swept for the policies
+that have it (tile-compensated, plain FP32, FP64).
 
     python -m paper_2411_18889_amd.tune --op force adjoint --n 65536 1048576
 
