@@ -11,9 +11,10 @@
 // the mass adjoints need anyway, and the factor -3 of T with the masses),
 // i.e. 21 VALU + 1/2 rsqrt per interaction against 34 + 1 one-sided.
 // The blocking, the work items (block pairs I <= J), the origin of the pair
-// arithmetic (the centroid of block I), the source-side sums carried through
-// the lanes and the fixed-order FP32 partials are those of the symmetric
-// force pass, with seven quantities instead of three:
+// arithmetic (tile-compensated policy: the centroid of block I), the
+// source-side sums carried through the lanes and the fixed-order partials
+// are those of the symmetric force pass, with seven quantities instead of
+// three:
 // a (3), J^T lam (3) and the mass-adjoint sum (1); the partials are in the
 // pair type (FP32; FP64 for the FP64 policy). The items run in bands of
 // block rows (SymLayout); after each band a fold kernel adds its partials
