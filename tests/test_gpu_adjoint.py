@@ -276,14 +276,19 @@ def test_adjoint_pass_full_size_against_oracle_rows(walk, prec):
         assert ea <= (1e-12 if prec == "f64" else 1e-5)
 
 
-@pytest.mark.parametrize("ipl,block", [(2, 128), (2, 256), (2, 512), (1, 256), (4, 128), (4, 256)])
-@pytest.mark.parametrize("prec", ("f64", "f32"))
+_SYM_ADJ = [(2, 128), (2, 256), (2, 512), (2, 1024), (1, 256), (1, 512), (4, 128), (4, 256),
+            (4, 512)]
+
+
+@pytest.mark.parametrize("prec,ipl,block", [("f64",) + s for s in _SYM_ADJ if s[1] <= 512] +
+                         [("f32",) + s for s in _SYM_ADJ])
 def test_adjoint_symmetric_pass_fp64_fp32(prec, ipl, block):
     """The symmetric adjoint pass in the FP64 and plain FP32 policies, in
-    explicit shapes (20037 particles: ragged last blocks): the entry pass
-    against the oracle's transposed Jacobians and against the one-sided
-    kernel, then one walked-back step (a pass with the force sums) against
-    the oracle's a(x) of the walked-back state."""
+    every shape the library has for them (20037 particles: ragged last
+    blocks; FP64 not in 16-wave workgroups): the entry pass against the
+    oracle's transposed Jacobians and against the one-sided kernel, then one
+    walked-back step (a pass with the force sums) against the oracle's a(x)
+    of the walked-back state."""
     n, eps, dt = 20000 + 37, 2.0 ** -8, 2.0 ** -9
     x, v, m = plummer_sphere(n, 903)
     xd, vd, md = to_dev(x, v, m, prec)
