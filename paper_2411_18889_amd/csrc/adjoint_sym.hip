@@ -162,18 +162,20 @@ SymShape choose_adjoint_sym_shape(int prec, int64_t n) {
     // within 5 % of it for either pass: 65536 4 x 2, 1.59 / 1.94 ms for
     // entry / walked-back pass against 2.55 / 2.91 one-sided; 2^20 4 x 4,
     // 399 / 464 ms against 631 / 708). FP64 (two FP32 registers a value)
-    // goes to four sinks per lane earlier, in smaller workgroups: 2 x 2 to
-    // 32768 (16384: 0.275 / 0.343 ms against 0.349 / 0.370 one-sided), 2 x 4
-    // to 163840 (65536: 3.03 / 3.93 against 4.92 / 5.35), 4 x 4 from there
-    // (262144: 45.8 / 57.2 against 78.2 / 84.8; 2^20: 733 / 915 against 1241
-    // / 1368).
+    // takes the fastest shape of the sweep at each size: 2 x 2 below 24576
+    // (16384: 0.275 / 0.343 ms against 0.349 / 0.370 one-sided), 4 x 2 below
+    // 49152 (24576: 0.530 / 0.663; 32768: 0.899 / 1.109, within 2.3 % of the
+    // fastest), 2 x 4 below 98304 (65536: 3.03 / 3.93 against 4.92 / 5.35),
+    // 4 x 4 from there (131072: 12.47 / 15.39; 262144: 45.8 / 57.2 against
+    // 78.2 / 84.8; 2^20: 733 / 915 against 1241 / 1368).
     if ((prec != NB_MIX_TILEC && prec != NB_F32 && prec != NB_F64) || n < 48 * 256 ||
         n > (int64_t(1) << 28))
         return SymShape{0, 0};
     if (prec == NB_F64) {
-        if (n < 32768) return SymShape{2, 2};   // 256
-        if (n < 163840) return SymShape{2, 4};  // 512
-        return SymShape{4, 4};                  // 1024
+        if (n < 24576) return SymShape{2, 2};  // 256
+        if (n < 49152) return SymShape{4, 2};  // 512
+        if (n < 98304) return SymShape{2, 4};  // 512
+        return SymShape{4, 4};                 // 1024
     }
     auto bi = [](const SymShape& c) { return (int64_t)c.waves * 64 * c.ipl; };
     if (n < 163840) {

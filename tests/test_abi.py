@@ -113,10 +113,11 @@ def test_workspace_size(L):
     n = 1 << 28
     assert L.nbody_workspace_size(2, n, TILEC) == 7 * n * 8 + 7 * 4 * (n + 262143 * 1024)
     # FP32 and FP64 take the symmetric adjoint too (FP64: FP64 partials, in
-    # blocks of 256 below 32768, 512 below 163840, 1024 from there; FP32 as
+    # blocks of 256 below 24576, 512 below 98304, 1024 from there; FP32 as
     # the tile-compensated policy); the running sums are FP64 for all three
     assert L.nbody_workspace_size(2, 16384, F64) == 64 * 7 * 16384 * 8
-    assert L.nbody_workspace_size(2, 1 << 17, F64) == 256 * 7 * (1 << 17) * 8
+    assert L.nbody_workspace_size(2, 32768, F64) == 64 * 7 * 32768 * 8
+    assert L.nbody_workspace_size(2, 1 << 17, F64) == 128 * 7 * (1 << 17) * 8
     assert L.nbody_workspace_size(2, 1 << 18, F64) == 256 * 7 * (1 << 18) * 8
     assert L.nbody_workspace_size(2, 1 << 20, F64) == 7 * (1 << 20) * 8 + G4
     assert L.nbody_workspace_size(2, 65536, F32) == 128 * 7 * 65536 * 4
@@ -313,7 +314,7 @@ def test_pass_info(L):
     assert L.nbody_pass_info(1, (1 << 28) + 1, TILEC, ctypes.byref(info)) == 0
     assert info.symmetric == 0
     # the FP64 and FP32 adjoint: symmetric too (FP64 with four sinks per
-    # lane from 32768); the compensated policies keep the one-sided kernel
+    # lane from 49152); the compensated policies keep the one-sided kernel
     assert L.nbody_pass_info(2, 1 << 20, F64, ctypes.byref(info)) == 0
     assert (info.symmetric, info.block, info.i_per_lane, info.block_particles) == (1, 256, 4, 1024)
     assert L.nbody_pass_info(2, 65536, F64, ctypes.byref(info)) == 0

@@ -45,7 +45,8 @@ def _gpu_grads(x, v, m, y, eps, dt, S, K, prec):
                                    (40000 + 77, 2, 1)])
 def test_adjoint_f64_matches_oracle(n, S, K):
     """Up to 1000 particles the one-sided kernel; from 12288 the symmetric
-    pass (FP64 partials; 40077: four sinks per lane, blocks of 512)."""
+    pass (FP64 partials; 40077: four waves of two sinks per lane, blocks of
+    512)."""
     x, v, m, y = _problem(n, 60 + n)
     eps, dt = 2.0 ** -5, 2.0 ** -7
     gx, gv, gm, _ = _gpu_grads(x, v, m, y, eps, dt, S, K, "f64")
