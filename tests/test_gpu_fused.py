@@ -20,7 +20,8 @@ from tests.gpu_util import DEV, to_dev
 pytestmark = pytest.mark.gpu
 
 # (n, policy, which pass): 5000 one-sided with a split source range;
-# 20000 the symmetric pass; f64 and f32 run the symmetric force too
+# 20000 the symmetric pass; f64 and f32 run the symmetric force and adjoint
+# too
 CASES = [(5000, "mix_tilec"), (20000, "mix_tilec"), (20000, "f64"), (20000, "f32"),
          (3000, "mix_kahan")]
 
@@ -43,7 +44,8 @@ def test_fused_kick_drift_is_bitwise(n, prec):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("n,prec", [(5000, "mix_tilec"), (20000, "mix_tilec"), (3000, "f64")])
+@pytest.mark.parametrize("n,prec", [(5000, "mix_tilec"), (20000, "mix_tilec"), (3000, "f64"),
+                                    (20000, "f64"), (20000, "f32")])
 def test_fused_reverse_drift_is_bitwise(n, prec):
     S = 4
     x, v, m = plummer_sphere(n, 820 + n % 7)
