@@ -209,3 +209,30 @@ def test_beyond_one_band_of_partials():
     ex, em = rel(host(lx)[:, idx] / c, jt), rel(host(lm)[idx] / c, gt)
     print("2^22 adjoint: J^T lam rel err %.3g, G^T lam %.3g" % (ex, em))
     assert ex <= 1e-4 and em <= 1e-4
+
+
+def test_fp64_adjoint_many_bands():
+    """2^21 particles in FP64: the symmetric adjoint's FP64 partials (blocks
+    of 1024, 240 GB in all) run as dozens of bands of the 4 GiB default
+    workspace; the entry pass's sampled rows against the oracle at the FP64
+    bar."""
+    from nbody_inputs import plummer_positions_device
+    prec, n, eps = "f64", 1 << 21, 2.0 ** -11
+    xd = plummer_positions_device(n, 761, DEV).to(torch.float64)
+    md = torch.full((n,), 1.0 / n, dtype=torch.float64, device=DEV)
+    info = nb.pass_info(2, n, prec)
+    assert info["symmetric"] == 1 and info["block_particles"] == 1024
+    lam = torch.tensor(np.random.default_rng(762).normal(size=(3, n)), device=DEV)
+    lx = torch.zeros_like(lam)
+    lm = torch.zeros(n, dtype=torch.float64, device=DEV)
+    vd, acc = torch.zeros_like(xd), torch.zeros_like(xd)
+    dt = 2.0 ** -12
+    print("2^21 FP64 adjoint pass", flush=True)
+    nb.step_adjoint(xd, vd, md, acc, lx, lam, lm, eps, dt, 0, prec=prec, entry_half=True)
+    c = 0.5 * dt
+    xh, mh = host(xd), host(md)
+    idx = sample_indices(xh, 256, 32, seed=763)
+    jt, gt = oracle.vjp_sampled(xh, mh, host(lam), eps, idx)
+    ex, em = rel(host(lx)[:, idx] / c, jt), rel(host(lm)[idx] / c, gt)
+    print("2^21 FP64 adjoint: J^T lam rel err %.3g, G^T lam %.3g" % (ex, em))
+    assert ex <= 1e-12 and em <= 1e-12
